@@ -1,0 +1,150 @@
+"""Throughput of the gfx950 SRK PT flash (flashes per second, FP64).
+
+One step = one flash of the whole batch (all stages of the path) with inputs
+resident in HBM.  Prints one JSON line (rank 0, one GPU).
+
+  python bench.py [--steps K] [--warmup W] [--workload nc8_1m|nc3_10k|nc10_1m]
+                  [--form persistent|plain] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "flashes/sec fwd and fwd+adjoint, Nc=8, FP64, ≤1e-10 vs oracle; FP64 roofline %"
+FP64_VECTOR_PEAK = 78.6e12   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+HBM_PEAK = 8.0e12
+
+
+def _kernel_sha() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2205_03090_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(workload: str, per_launch_flashes: int):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, or
+    None when they are missing or were taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_sha") != _kernel_sha():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(w, budget_s: float = 12.0):
+    """The oracle, as it stands, on a bounded leading sample of the workload,
+    on the host's cores."""
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    chunk = 20_000
+    done, t0 = 0, time.perf_counter()
+    while done < w.n and time.perf_counter() - t0 < budget_s:
+        sub = w.subset(np.arange(done, min(done + chunk, w.n)))
+        oracle.flash(sub, threads=threads)
+        done += sub.n
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "flashes/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {done} mixtures of {w.name} ({dt:.1f} s wall)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="nc8_1m")
+    ap.add_argument("--form", default="persistent", choices=["persistent", "plain"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--check", type=int, default=2000, help="mixtures checked against the oracle")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(mixtures are independent: a multi-GPU run shards them with no exchange)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2205_03090_amd import _capi, api, workloads
+
+    makers = {"nc8_1m": workloads.nc8_workload, "nc3_10k": workloads.nc3_workload,
+              "nc10_1m": workloads.nc10_workload}
+    w = makers[args.workload]()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev).contiguous()
+    z, T, P, Tc, Pc, om, kij = map(t, (w.z, w.T, w.P, w.Tc, w.Pc, w.omega, w.kij))
+    form = _capi.FORM_PERSISTENT if args.form == "persistent" else _capi.FORM_PLAIN
+    out = api.flash(z, T, P, Tc, Pc, om, kij, form=form)
+    torch.cuda.synchronize()
+    for _ in range(max(0, args.warmup - 1)):
+        api.flash(z, T, P, Tc, Pc, om, kij, form=form, out=out)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record(stream)
+        api.flash(z, T, P, Tc, Pc, om, kij, form=form, out=out)
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    avg_ms = float(np.mean(launch_ms))
+    value = w.n * args.steps / wall
+
+    flops = out.flops.to(torch.int64).sum().item()
+    g = {k: getattr(out, k).cpu().numpy() for k in ("label", "iters", "status")}
+    achieved = flops / (avg_ms * 1e-3)
+    traffic = _traffic(args.workload, w.n)
+
+    rec = {
+        "metric": METRIC, "value": value, "unit": "flashes/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "nc": w.nc, "form": args.form},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK,
+                     "traffic": traffic, "flops_per_flash": flops / w.n,
+                     "kernel_ms": avg_ms},
+        "two_phase_frac": float((g["label"] == 1).mean()),
+        "status_counts": {k: int(((g["status"].astype(np.int64) & 0xffff) & v != 0).sum())
+                          for k, v in _capi.ST.items()},
+    }
+    if args.check > 0:
+        import oracle
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from parity import compare, gpu_to_numpy
+        gg = gpu_to_numpy(out)
+        idx = np.sort(np.random.Generator(np.random.PCG64(123)).choice(w.n, min(args.check, w.n),
+                                                                       replace=False))
+        o = oracle.flash(w.subset(idx), threads=min(16, os.cpu_count() or 1), want_min_tpd=1)
+        rep = compare(gg, o, idx, verbose=False)
+        rec["parity"] = {k: rep[k] for k in ("n", "label_mismatch", "value_mismatch",
+                                             "single_mismatch", "max_err", "ss_path_agree")}
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

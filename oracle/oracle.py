@@ -21,7 +21,7 @@ _lock = threading.Lock()
 class OrcOpts(C.Structure):
     _fields_ = [("max_pre_ss", C.c_int32), ("max_ss", C.c_int32),
                 ("max_newton", C.c_int32), ("dem_every", C.c_int32),
-                ("want_min_tpd", C.c_int32), ("pad_", C.c_int32),
+                ("want_min_tpd", C.c_int32), ("max_newton_split", C.c_int32),
                 ("tol_sa_ss", C.c_double), ("tol_sa_tr", C.c_double),
                 ("tol_split_ss", C.c_double), ("tol_split", C.c_double),
                 ("eps_tm", C.c_double)]

@@ -37,8 +37,11 @@
  *   R3  dominant-eigenvalue acceleration: at every 5th successive
  *       substitution update u (u >= 2), lambda = (s_u . s_u)/(s_{u-1} . s_u)
  *       with s the plain update step; if 0 < lambda < 1 the update is
- *       extended by s_u lambda/(1-lambda).  Not applied in the three initial
- *       iterations.
+ *       extended by s_u lambda/(1-lambda).  The extrapolated point is kept
+ *       only if its objective (tm for a stability trial, G per unit feed for
+ *       the split) is lower than at the point the update started from;
+ *       otherwise the plain update is taken (the rejected evaluation is not
+ *       counted).  Not applied in the three initial iterations.
  *   R4  a stability trial is unstable when tm < -eps_tm (eps_tm = 1e-10).
  *   R5  trials start from the Wilson K; the initial successive substitution
  *       stops at the first iteration whose Rachford-Rice root leaves (0,1)
@@ -78,7 +81,7 @@ typedef struct {
     int32_t max_newton;      /* cap of the oracle's Newton stand-ins       */
     int32_t dem_every;       /* acceleration period (5), 0 = off           */
     int32_t want_min_tpd;    /* also compute the min-TPD diagnostic        */
-    int32_t pad_;
+    int32_t max_newton_split;/* cap of the split's Newton stand-in         */
     double tol_sa_ss;        /* max |d tm / d W| (1e-6)                    */
     double tol_sa_tr;        /* max |g| in beta variables (1e-6)           */
     double tol_split_ss;     /* max |K_new/K - 1| (1e-8)                   */
@@ -363,17 +366,27 @@ static int orc_sa_ss(const orc_eos *e, const double *d, double *lnW,
 {
     int nc = e->nc;
     double grad[ORC_NCMAX], step[ORC_NCMAX], prev[ORC_NCMAX];
+    int upd = 0, pending = 0;
+    double tm_before = 0.0, ext_applied = 0.0;
     *n_upd = 0;
-    for (int u = 0;; ++u) {
+    for (int guard = 0; guard < 4 * o->max_ss + 8; ++guard) {
         double tm = orc_tm_eval(e, lnW, d, grad, NULL);
         *tm_out = tm;
         if (tm < -o->eps_tm) return ORC_TRIAL_NEGATIVE;
         double gmax = 0.0;
         for (int i = 0; i < nc; ++i) if (fabs(grad[i]) > gmax) gmax = fabs(grad[i]);
         if (gmax < o->tol_sa_ss) return ORC_TRIAL_STATIONARY;
-        if (u == o->max_ss) return ORC_TRIAL_UNCONV;
+        if (pending) {
+            /* R3: an extrapolated point is kept only if it lowers tm */
+            pending = 0;
+            if (!(tm < tm_before)) {
+                for (int i = 0; i < nc; ++i) lnW[i] -= ext_applied * prev[i];
+                continue;
+            }
+        }
+        if (upd == o->max_ss) return ORC_TRIAL_UNCONV;
         for (int i = 0; i < nc; ++i) step[i] = -grad[i];
-        int upd = u + 1;
+        ++upd;
         double ext = 0.0;
         if (o->dem_every > 0 && upd >= 2 && upd % o->dem_every == 0) {
             double num = 0.0, den = 0.0;
@@ -385,8 +398,10 @@ static int orc_sa_ss(const orc_eos *e, const double *d, double *lnW,
             lnW[i] += step[i] + ext * step[i];
             prev[i] = step[i];
         }
+        if (ext > 0.0) { pending = 1; tm_before = tm; ext_applied = ext; }
         *n_upd = upd;
     }
+    return ORC_TRIAL_UNCONV;
 }
 
 /* Gradient of tm with respect to beta = 2 sqrt(W) (Appendix B.1, eq.
@@ -452,6 +467,7 @@ static int orc_minimise(const orc_minprob *pr, double *x, int *n_it, double *f_o
         if (local) {
             if (gmax < best) { best = gmax; stall = 0; }
             else if (++stall >= 3) return ORC_MIN_STUCK;
+            mu = 0.0;   /* plain Newton first near the stationary point */
         }
         if (it == pr->max_it) return ORC_MIN_CAP;
         *n_it = it + 1;
@@ -496,9 +512,13 @@ static int orc_minimise(const orc_minprob *pr, double *x, int *n_it, double *f_o
             for (int i = 0; i < n; ++i) xt[i] = x[i] + a * p[i];
             double ft = pr->fn(pr->ctx, xt, gt);
             if (local) {
-                double tmax = 0.0;
-                for (int i = 0; i < n; ++i) if (fabs(gt[i]) > tmax) tmax = fabs(gt[i]);
-                acc = tmax < gmax;
+                double tmax = 0.0, t2 = 0.0, g2 = 0.0;
+                for (int i = 0; i < n; ++i) {
+                    if (fabs(gt[i]) > tmax) tmax = fabs(gt[i]);
+                    t2 += gt[i] * gt[i];
+                    g2 += g[i] * g[i];
+                }
+                acc = tmax < gmax || t2 < g2;
             } else {
                 acc = ft <= f + 1e-4 * a * slope;
             }
@@ -610,21 +630,37 @@ static int orc_split_ss(const orc_eos *e, const double *z, double *lnK,
     int nc = e->nc;
     double K[ORC_NCMAX], x[ORC_NCMAX], y[ORC_NCMAX], lx[ORC_NCMAX], ly[ORC_NCMAX];
     double step[ORC_NCMAX], prev[ORC_NCMAX];
+    int u = 0, pending = 0;
+    double g_before = 0.0, ext_applied = 0.0;
     *conv = 0; *rr_fail = 0;
-    int u;
-    for (u = 1; u <= o->max_ss; ++u) {
+    for (int guard = 0; guard < 4 * o->max_ss + 8 && u < o->max_ss; ++guard) {
         double th;
         for (int i = 0; i < nc; ++i) K[i] = exp(lnK[i]);
-        if (orc_rr_solve(nc, z, K, &th) != 0) { *rr_fail = 1; return u - 1; }
+        if (orc_rr_solve(nc, z, K, &th) != 0) { *rr_fail = 1; return u; }
         orc_xy_from_k(nc, z, K, th, x, y);
         orc_phase(e, x, lx, NULL);
         orc_phase(e, y, ly, NULL);
+        /* reduced Gibbs energy per unit feed at this point (eq. gibbs) */
+        double G = 0.0;
+        if (pending || (o->dem_every > 0 && (u + 1) >= 2 && (u + 1) % o->dem_every == 0)) {
+            for (int i = 0; i < nc; ++i)
+                G += (1.0 - th) * x[i] * (log(x[i]) + lx[i]) + th * y[i] * (log(y[i]) + ly[i]);
+        }
+        if (pending) {
+            /* R3: an extrapolated point is kept only if it lowers G */
+            pending = 0;
+            if (!(G < g_before)) {
+                for (int i = 0; i < nc; ++i) lnK[i] -= ext_applied * prev[i];
+                continue;
+            }
+        }
         double dmax = 0.0;
         for (int i = 0; i < nc; ++i) {
             step[i] = (lx[i] - ly[i]) - lnK[i];
             double q = fabs(exp(step[i]) - 1.0);
             if (q > dmax) dmax = q;
         }
+        ++u;
         double ext = 0.0;
         if (o->dem_every > 0 && u >= 2 && u % o->dem_every == 0) {
             double num = 0.0, den = 0.0;
@@ -634,8 +670,9 @@ static int orc_split_ss(const orc_eos *e, const double *z, double *lnK,
         }
         for (int i = 0; i < nc; ++i) { lnK[i] += step[i] + ext * step[i]; prev[i] = step[i]; }
         if (dmax < o->tol_split_ss) { *conv = 1; return u; }
+        if (ext > 0.0) { pending = 1; g_before = G; ext_applied = ext; }
     }
-    return o->max_ss;
+    return u;
 }
 
 /* G and its gradient over the vapour mole numbers (eqs. gibbs, split_grad). */
@@ -667,7 +704,7 @@ static int orc_split_newton(const orc_eos *e, const double *z, double *nV,
     for (int i = 0; i < nc; ++i) lo[i] = 0.0;
     orc_split_ctx c = {e, z};
     orc_minprob pr = {nc, orc_split_obj, orc_split_metric, &c, lo, z, 1e-7,
-                      o->tol_split, -INFINITY, o->max_newton};
+                      o->tol_split, -INFINITY, o->max_newton_split};
     int rc = orc_minimise(&pr, nV, n_it, &G);
     if (rc == ORC_MIN_TOL) return 0;
     if (rc == ORC_MIN_STUCK) {
@@ -853,7 +890,8 @@ int orc_flash_one(int nc, const double *z_in, double T, double P,
     res->info[ORC_I_NT_SPLIT] = nnt;
     double bv = 0.0;
     for (int i = 0; i < nc; ++i) bv += nV[i];
-    if (!(bv > 0.0 && bv < 1.0)) {
+    /* a phase holding less than 1e-10 of the feed: degenerate split */
+    if (!(bv > 1e-10 && bv < 1.0 - 1e-10)) {
         res->info[ORC_I_FLAGS] = (int32_t)(flags | ORC_SPLIT_FAILED);
         return 0;
     }
@@ -896,7 +934,7 @@ void orc_default_opts(orc_opts *o)
     o->max_newton = 200;
     o->dem_every = 5;
     o->want_min_tpd = 0;
-    o->pad_ = 0;
+    o->max_newton_split = 200;
     o->tol_sa_ss = 1e-6;
     o->tol_sa_tr = 1e-6;
     o->tol_split_ss = 1e-8;

@@ -1,0 +1,9 @@
+"""MI355X (gfx950) isothermal two-phase PT flash with the SRK equation of state.
+
+The compute path is the HIP library built from ``csrc/`` (C ABI in
+``include/ptflash.h``); this package only binds it to PyTorch tensors.
+"""
+from . import _capi  # noqa: F401
+from .api import FlashResult, eval_phase, flash  # noqa: F401
+
+__all__ = ["flash", "eval_phase", "FlashResult"]

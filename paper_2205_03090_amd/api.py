@@ -1,0 +1,108 @@
+"""PyTorch front end: device memory and streams from torch, all compute in HIP.
+
+``flash`` runs the SRK PT flash on tensors that live on the current HIP
+device and stream; ``eval_phase`` exposes the phase model used inside it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _capi
+
+
+@dataclass
+class FlashResult:
+    label: torch.Tensor     # (n,) int8: 0 single phase, 1 two-phase
+    beta: torch.Tensor      # (n,) float64: vapour fraction, -1 for single phase
+    x: torch.Tensor         # (n, nc) float64 liquid-like composition
+    y: torch.Tensor         # (n, nc) float64 vapour-like composition
+    iters: torch.Tensor     # (n, 8) int16 iteration counters (see _capi.IT_NAMES)
+    status: torch.Tensor    # (n,) int16 status bits (see _capi.ST)
+    flops: torch.Tensor     # (n,) int32 algorithmic flops per mixture
+    factor: torch.Tensor | None  # (n, nc(nc+1)/2) Cholesky factor or None
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _f64(t, device):
+    return torch.as_tensor(t, dtype=torch.float64, device=device).contiguous()
+
+
+def _stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def make_problem(z, T, P, Tc, Pc, omega, kij):
+    n, nc = z.shape
+    per = 1 if Tc.dim() == 2 else 0
+    p = _capi.Problem(n=n, nc=nc, props_per_mixture=per, z=_ptr(z).value, T=_ptr(T).value,
+                      P=_ptr(P).value, Tc=_ptr(Tc).value, Pc=_ptr(Pc).value,
+                      omega=_ptr(omega).value, kij=_ptr(kij).value)
+    return p
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    buf = torch.empty(max(int(nbytes), 1) + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + max(int(nbytes), 1)]
+
+
+def flash(z, T, P, Tc, Pc, omega, kij, *, keep_factor: bool = False, stream=None,
+          out: FlashResult | None = None, **opts) -> FlashResult:
+    """Isothermal two-phase SRK flash of n mixtures on the current GPU.
+
+    z (n, nc), T (n,), P (n,) and the component set Tc, Pc, omega (nc,), kij
+    (nc, nc) are float64 tensors (moved to the GPU if needed).  Keyword
+    options override ptflash_default_options (e.g. form=_capi.FORM_PLAIN)."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    z, T, P = _f64(z, dev), _f64(T, dev), _f64(P, dev)
+    Tc, Pc, omega, kij = (_f64(a, dev) for a in (Tc, Pc, omega, kij))
+    n, nc = z.shape
+    o = _capi.default_options(keep_factor=int(keep_factor), **opts)
+    prob = make_problem(z, T, P, Tc, Pc, omega, kij)
+    if out is None:
+        out = FlashResult(
+            label=torch.empty(n, dtype=torch.int8, device=dev),
+            beta=torch.empty(n, dtype=torch.float64, device=dev),
+            x=torch.empty((n, nc), dtype=torch.float64, device=dev),
+            y=torch.empty((n, nc), dtype=torch.float64, device=dev),
+            iters=torch.empty((n, _capi.NITERS), dtype=torch.int16, device=dev),
+            status=torch.empty(n, dtype=torch.int16, device=dev),
+            flops=torch.empty(n, dtype=torch.int32, device=dev),
+            factor=(torch.full((n, nc * (nc + 1) // 2), float("nan"), dtype=torch.float64,
+                               device=dev) if keep_factor else None))
+    res = _capi.Result(label=_ptr(out.label).value, beta=_ptr(out.beta).value,
+                       x=_ptr(out.x).value, y=_ptr(out.y).value, iters=_ptr(out.iters).value,
+                       status=_ptr(out.status).value, flops=_ptr(out.flops).value,
+                       factor=None if out.factor is None else _ptr(out.factor).value)
+    L = _capi.lib()
+    ws_bytes = L.ptflash_workspace_bytes(C.byref(prob), C.byref(o))
+    ws = _workspace(ws_bytes, dev)
+    rc = L.ptflash_flash(C.byref(prob), C.byref(o), C.byref(res), _ptr(ws), ws_bytes,
+                         _stream_handle(stream))
+    _capi.check(rc, "ptflash_flash")
+    out._keepalive = (z, T, P, Tc, Pc, omega, kij, ws)  # until the stream is done
+    return out
+
+
+def eval_phase(c, T, P, Tc, Pc, omega, kij, *, derivs: bool = True, stream=None):
+    """ln phi (n, nc), Z (n,) and Phi = n d ln phi/d n (n, nc, nc) of the SRK
+    phase model at compositions c (n, nc)."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    c, T, P = _f64(c, dev), _f64(T, dev), _f64(P, dev)
+    Tc, Pc, omega, kij = (_f64(a, dev) for a in (Tc, Pc, omega, kij))
+    n, nc = c.shape
+    lnphi = torch.empty((n, nc), dtype=torch.float64, device=dev)
+    Z = torch.empty(n, dtype=torch.float64, device=dev)
+    phi = torch.empty((n, nc, nc), dtype=torch.float64, device=dev) if derivs else None
+    rc = _capi.lib().ptflash_eval_phase(n, nc, _ptr(c), _ptr(T), _ptr(P), _ptr(Tc), _ptr(Pc),
+                                        _ptr(omega), _ptr(kij), _ptr(lnphi), _ptr(Z),
+                                        _ptr(phi), _stream_handle(stream))
+    _capi.check(rc, "ptflash_eval_phase")
+    return lnphi, Z, phi

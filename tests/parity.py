@@ -1,0 +1,82 @@
+"""Comparison of GPU flash results with the CPU oracle (shared by the GPU
+tests, the smoke check and the benchmark's checks).
+
+Rule: labels must be identical wherever the oracle's |min TPD| > 1e-9; where
+both sides report two phases (outside the same band), beta, x and y agree
+within 1e-10 absolute; where both report one phase, beta = -1 and
+x = y = z/sum(z) bit for bit.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+TOL = 1e-10
+BAND = 1e-9
+
+
+def gpu_to_numpy(r):
+    out = {k: getattr(r, k).detach().cpu().numpy() for k in
+           ("label", "beta", "x", "y", "iters", "status", "flops")}
+    if r.factor is not None:
+        out["factor"] = r.factor.detach().cpu().numpy()
+    return out
+
+
+def compare(g: dict, o: dict, idx=None, verbose: bool = True) -> dict:
+    """g: GPU arrays (full batch); o: oracle arrays for rows idx (or all)."""
+    if idx is None:
+        idx = np.arange(len(o["label"]))
+    gl, ol = g["label"][idx].astype(int), o["label"].astype(int)
+    mt = o["min_tpd"]
+    decisive = ~(np.abs(mt) <= BAND)          # NaN (not computed) counts as decisive
+    lab_bad = np.where(decisive & (gl != ol))[0]
+    # values are compared where both report two phases outside the band
+    # (within it G is flat to ~1e-9 and distinct stationary points compete)
+    both2 = np.where((gl == 1) & (ol == 1) & decisive)[0]
+    both1 = np.where((gl == 0) & (ol == 0))[0]
+    db = np.abs(g["beta"][idx][both2] - o["beta"][both2]) if len(both2) else np.zeros(0)
+    dx = np.abs(g["x"][idx][both2] - o["x"][both2]).max(1) if len(both2) else np.zeros(0)
+    dy = np.abs(g["y"][idx][both2] - o["y"][both2]).max(1) if len(both2) else np.zeros(0)
+    err = np.maximum(db, np.maximum(dx, dy))
+    val_bad = both2[err > TOL]
+    one_bad = both1[(g["beta"][idx][both1] != -1.0) |
+                    np.any(g["x"][idx][both1] != o["x"][both1], axis=1) |
+                    np.any(g["y"][idx][both1] != o["y"][both1], axis=1)]
+    rep = dict(n=len(idx), two_phase=int(len(both2)), single=int(len(both1)),
+               label_mismatch=int(len(lab_bad)), value_mismatch=int(len(val_bad)),
+               single_mismatch=int(len(one_bad)),
+               max_err=float(err.max()) if len(err) else 0.0,
+               band_excluded=int((~decisive).sum()))
+    # path agreement of the substitution counters (same algorithm on both sides)
+    oi, gi = o["info"], g["iters"][idx]
+    same = (gi[:, 0] == oi[:, 1]) & (gi[:, 1] == oi[:, 2]) & (gi[:, 3] == oi[:, 4]) & \
+           (gi[:, 5] == oi[:, 6])
+    rep["ss_path_agree"] = float(same.mean()) if len(same) else 1.0
+    if verbose and (len(lab_bad) or len(val_bad) or len(one_bad)):
+        for k in list(lab_bad[:5]) + list(val_bad[:5]) + list(one_bad[:3]):
+            m = idx[k]
+            print(f"  row {m}: gpu label {gl[k]} beta {g['beta'][m]:.12g} iters "
+                  f"{g['iters'][m].tolist()} status {int(g['status'][m]) & 0xffff:#x} | oracle "
+                  f"label {ol[k]} beta {o['beta'][k]:.12g} min_tpd {mt[k]:.3e} info "
+                  f"{o['info'][k].tolist()} | err {err[np.searchsorted(both2, k)] if k in both2 else 0:.2e}",
+                  flush=True)
+    return rep
+
+
+def invariants(w, g) -> dict:
+    """Checks every GPU output: material balance and normalisation of
+    two-phase results; single-phase results equal the normalised feed."""
+    lab = g["label"]
+    two = lab == 1
+    z = w.z / np.cumsum(w.z, axis=1)[:, -1:]
+    b = g["beta"][two][:, None]
+    mb = np.abs((1 - b) * g["x"][two] + b * g["y"][two] - z[two]).max() if two.any() else 0.0
+    sx = np.abs(g["x"][two].sum(1) - 1).max() if two.any() else 0.0
+    sy = np.abs(g["y"][two].sum(1) - 1).max() if two.any() else 0.0
+    brange = bool(np.all((g["beta"][two] > 0) & (g["beta"][two] < 1)))
+    one = lab == 0
+    single_ok = bool(np.all(g["beta"][one] == -1.0) and np.array_equal(g["x"][one], z[one])
+                     and np.array_equal(g["y"][one], z[one]))
+    return dict(two_phase_frac=float(two.mean()), mass_balance=float(mb), sum_x=float(sx),
+                sum_y=float(sy), beta_in_range=brange, single_ok=single_ok,
+                labels_valid=bool(np.all((lab == 0) | (lab == 1))))

@@ -1,0 +1,55 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+that include/ptflash.h declares, and rejects malformed calls before touching
+the GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2205_03090_amd import _capi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "ptflash.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ptflash_\w+)\s*\(", text)))
+
+
+def test_header_declarations_are_exported():
+    decl = _declared_functions()
+    assert set(decl) == set(_capi.EXPORTS)
+    L = _capi.lib()
+    for name in decl:
+        assert hasattr(L, name), name
+
+
+def test_default_options_are_the_papers():
+    o = _capi.default_options()
+    assert (o.max_pre_ss, o.max_ss, o.max_tr_sa, o.max_tr_split) == (3, 9, 20, 20)
+    assert (o.tol_sa_ss, o.tol_sa_tr, o.tol_split_ss, o.tol_split_tr) == (1e-6, 1e-6, 1e-8, 1e-8)
+    assert o.dem_every == 5 and o.eps_tm == 1e-10 and o.form == _capi.FORM_PERSISTENT
+
+
+def test_rejects_malformed_calls_without_gpu():
+    L = _capi.lib()
+    o = _capi.default_options()
+    r = _capi.Result()
+    assert L.ptflash_flash(None, C.byref(o), C.byref(r), None, 0, None) == 1
+    p = _capi.Problem(n=-1, nc=3)
+    assert L.ptflash_flash(C.byref(p), C.byref(o), C.byref(r), None, 0, None) == 1
+    p = _capi.Problem(n=5, nc=1, z=8, T=8, P=8, Tc=8, Pc=8, omega=8, kij=8)
+    assert L.ptflash_flash(C.byref(p), C.byref(o), C.byref(r), None, 0, None) == 2
+    p = _capi.Problem(n=5, nc=L.ptflash_max_nc() + 1, z=8, T=8, P=8, Tc=8, Pc=8, omega=8, kij=8)
+    assert L.ptflash_flash(C.byref(p), C.byref(o), C.byref(r), None, 0, None) == 2
+    p = _capi.Problem(n=5, nc=3, z=8, T=8, P=8, Tc=8, Pc=8, omega=8, kij=8)
+    r = _capi.Result(label=8, beta=8, x=8, y=8)
+    assert L.ptflash_flash(C.byref(p), C.byref(o), C.byref(r), None, 0, None) == 3
+    bad = _capi.default_options(max_pre_ss=0)
+    assert L.ptflash_flash(C.byref(p), C.byref(bad), C.byref(r), None, 0, None) == 1
+    p0 = _capi.Problem(n=0, nc=3)
+    assert L.ptflash_flash(C.byref(p0), C.byref(o), C.byref(r), None, 0, None) == 0
+    assert L.ptflash_workspace_bytes(C.byref(p), C.byref(o)) >= 8
+    assert L.ptflash_strerror(3) == b"workspace too small"
