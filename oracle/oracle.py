@@ -56,6 +56,9 @@ def lib():
             L.orc_split_residual.argtypes = [C.c_int32, _D, _D, _D, _D, C.c_double, C.c_double, _D, _D, _D]
             L.orc_split_residual.restype = C.c_double
             L.orc_ninfo.restype = C.c_int
+            L.orc_flash_jacobian.argtypes = [C.c_int32, _D, C.c_double, C.c_double, _D, _D, _D,
+                                             _D, C.c_double, _D, _D]
+            L.orc_flash_jacobian.restype = C.c_int
             L.orc_flash_batch.argtypes = [C.c_int64, C.c_int32, _D, _D, _D, _D, _D, _D, _D,
                                           C.c_int32, C.POINTER(OrcOpts), C.c_void_p, _D, _D,
                                           _D, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64]
@@ -154,3 +157,18 @@ def flash(w, opts: OrcOpts | None = None, threads: int | None = None, **kw):
         with ThreadPoolExecutor(threads) as ex:
             list(ex.map(run, range(threads)))
     return dict(label=label, beta=beta, x=x, y=y, min_tpd=mtpd, info=info)
+
+
+def flash_jacobian(Tc, Pc, omega, kij, z, T, P, beta, y):
+    """Jacobian of (beta, x, y) of a converged two-phase result with respect
+    to p = (z_raw[nc], T, P, k_ab for a < b), by the implicit function
+    theorem on the equal-fugacity system (finite-difference partials)."""
+    Tc, Pc, omega, kij, z, y = map(_f64, (Tc, Pc, omega, kij, z, y))
+    nc = len(z)
+    npar = nc + 2 + nc * (nc - 1) // 2
+    J = np.zeros((1 + 2 * nc, npar))
+    rc = lib().orc_flash_jacobian(nc, _p(z), T, P, _p(Tc), _p(Pc), _p(omega), _p(kij),
+                                  float(beta), _p(y), _p(J))
+    if rc != 0:
+        raise RuntimeError("singular split Jacobian")
+    return J

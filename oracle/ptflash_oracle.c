@@ -1018,3 +1018,110 @@ double orc_split_residual(int32_t nc, const double *Tc, const double *Pc,
     orc_split_res(&e, z, nV, r, &G);
     return G;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Dense Jacobian of a converged split (implicit function theorem)         */
+/* ---------------------------------------------------------------------- */
+
+/* Parameters p = (z_raw[nc], T, P, k_ab for a < b).  The split is the root
+ * u of r(u; z~, T, P, k) = ln y + ln phi(y) - ln x - ln phi(x) = 0 (eq.
+ * eq_cond in logarithms, eq. split_grad) with y = u / sum u and
+ * x = (z~ - u) / sum(z~ - u), z~ = z_raw / sum z_raw; the outputs are
+ * o = (beta = sum u, x, y).  By the implicit function theorem
+ * du/dp = -(dr/du)^-1 dr/dp.  The partial Jacobians dr/du and dr/d(z~, T,
+ * P, k) are central differences (steps of 1e-5 relative to the smallest
+ * quantity they move: u_j and the liquid moles z~ - u for u and z~); dr/dz
+ * follows from dr/dz~ through the normalisation; the systems are solved by
+ * Gaussian elimination; the outputs are differentiated in closed form:
+ *   d beta = sum du, dy = (du - y d beta)/beta,
+ *   dx = (dn^L - x sum dn^L)/(1 - beta), dn^L = dz~ - du. */
+
+static void orc_res_zt(int nc, const double *u, const double *zt, double T, double P,
+                       const double *Tc, const double *Pc, const double *omega,
+                       const double *kij, double *r)
+{
+    orc_eos e;
+    orc_eos_setup(nc, Tc, Pc, omega, kij, T, P, &e);
+    orc_split_res(&e, zt, u, r, NULL);
+}
+
+/* J (row-major, (1+2nc) x (nc+2+nc(nc-1)/2)) of the outputs (beta, x, y) of a
+ * converged two-phase result given in the library's orientation (y the
+ * phase whose mole numbers are u = beta y).  Returns 0, or 1 when dr/du is
+ * singular. */
+int orc_flash_jacobian(int32_t nc, const double *zraw, double T, double P,
+                       const double *Tc, const double *Pc, const double *omega,
+                       const double *kij, double beta, const double *y, double *J)
+{
+    int np = nc + 2 + nc * (nc - 1) / 2, no = 1 + 2 * nc;
+    double u[ORC_NCMAX], zt[ORC_NCMAX], s = 0.0, nlmin = INFINITY;
+    double Ju[ORC_NCMAX * ORC_NCMAX], rp[ORC_NCMAX], rm[ORC_NCMAX], ut[ORC_NCMAX];
+    double Jz[ORC_NCMAX * ORC_NCMAX], zp[ORC_NCMAX];
+    for (int i = 0; i < nc; ++i) s += zraw[i];
+    for (int i = 0; i < nc; ++i) {
+        zt[i] = zraw[i] / s;
+        u[i] = beta * y[i];
+        nlmin = fmin(nlmin, zt[i] - u[i]);
+    }
+    for (int j = 0; j < nc; ++j) {
+        double h = 1e-5 * fmin(u[j], zt[j] - u[j]);
+        memcpy(ut, u, sizeof(double) * nc);
+        ut[j] = u[j] + h; orc_res_zt(nc, ut, zt, T, P, Tc, Pc, omega, kij, rp);
+        ut[j] = u[j] - h; orc_res_zt(nc, ut, zt, T, P, Tc, Pc, omega, kij, rm);
+        for (int i = 0; i < nc; ++i) Ju[i * nc + j] = (rp[i] - rm[i]) / (2.0 * h);
+    }
+    /* dr/dz~_k */
+    for (int k = 0; k < nc; ++k) {
+        double h = 1e-5 * fmin(zt[k] - u[k], nlmin * 1e3);
+        memcpy(zp, zt, sizeof(double) * nc);
+        zp[k] = zt[k] + h; orc_res_zt(nc, u, zp, T, P, Tc, Pc, omega, kij, rp);
+        zp[k] = zt[k] - h; orc_res_zt(nc, u, zp, T, P, Tc, Pc, omega, kij, rm);
+        for (int i = 0; i < nc; ++i) Jz[i * nc + k] = (rp[i] - rm[i]) / (2.0 * h);
+    }
+    double k2[ORC_NCMAX * ORC_NCMAX], drp[ORC_NCMAX], du[ORC_NCMAX], dzt[ORC_NCMAX];
+    double M[ORC_NCMAX * ORC_NCMAX];
+    int pa = 0, pb = 0;
+    for (int q = 0; q < np; ++q) {
+        for (int i = 0; i < nc; ++i) dzt[i] = 0.0;
+        if (q < nc) {
+            /* dz~/dz_q = (e_q - z~)/sum z */
+            for (int i = 0; i < nc; ++i) dzt[i] = ((i == q ? 1.0 : 0.0) - zt[i]) / s;
+            for (int i = 0; i < nc; ++i) {
+                double a = 0.0;
+                for (int k = 0; k < nc; ++k) a += Jz[i * nc + k] * dzt[k];
+                drp[i] = a;
+            }
+        } else if (q == nc || q == nc + 1) {
+            double h = 1e-5 * (q == nc ? T : P);
+            double Tp = T + (q == nc ? h : 0.0), Pp = P + (q == nc + 1 ? h : 0.0);
+            double Tm = T - (q == nc ? h : 0.0), Pm = P - (q == nc + 1 ? h : 0.0);
+            orc_res_zt(nc, u, zt, Tp, Pp, Tc, Pc, omega, kij, rp);
+            orc_res_zt(nc, u, zt, Tm, Pm, Tc, Pc, omega, kij, rm);
+            for (int i = 0; i < nc; ++i) drp[i] = (rp[i] - rm[i]) / (2.0 * h);
+        } else {
+            /* symmetric perturbation of k_ab = k_ba */
+            if (q == nc + 2) { pa = 0; pb = 1; }
+            else if (++pb == nc) { ++pa; pb = pa + 1; }
+            double h = 1e-5;
+            memcpy(k2, kij, sizeof(double) * nc * nc);
+            k2[pa * nc + pb] += h; k2[pb * nc + pa] += h;
+            orc_res_zt(nc, u, zt, T, P, Tc, Pc, omega, k2, rp);
+            k2[pa * nc + pb] -= 2.0 * h; k2[pb * nc + pa] -= 2.0 * h;
+            orc_res_zt(nc, u, zt, T, P, Tc, Pc, omega, k2, rm);
+            for (int i = 0; i < nc; ++i) drp[i] = (rp[i] - rm[i]) / (2.0 * h);
+        }
+        for (int i = 0; i < nc; ++i) du[i] = -drp[i];
+        memcpy(M, Ju, sizeof(double) * nc * nc);
+        if (orc_gepp(nc, M, du)) return 1;
+        double db = 0.0, dnl = 0.0;
+        for (int i = 0; i < nc; ++i) { db += du[i]; dnl += dzt[i] - du[i]; }
+        J[0 * np + q] = db;
+        for (int i = 0; i < nc; ++i) {
+            double xi = (zt[i] - u[i]) / (1.0 - beta);
+            J[(1 + i) * np + q] = ((dzt[i] - du[i]) - xi * dnl) / (1.0 - beta);
+            J[(1 + nc + i) * np + q] = (du[i] - y[i] * db) / beta;
+        }
+    }
+    (void)no;
+    return 0;
+}
