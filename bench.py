@@ -1,10 +1,14 @@
 """Throughput of the gfx950 SRK PT flash (flashes per second, FP64).
 
 One step = one flash of the whole batch (all stages of the path) with inputs
-resident in HBM.  Prints one JSON line (rank 0, one GPU).
+resident in HBM.  Prints one JSON line (one GPU): `value` is the forward
+throughput of the persistent form; `fwd_adjoint` times forward (keeping the
+factor) + implicit-function backward; `plain_form` times the plain
+one-launch-per-stage-iteration form on the same inputs.
 
   python bench.py [--steps K] [--warmup W] [--workload nc8_1m|nc3_10k|nc10_1m]
-                  [--form persistent|plain] [--no-cpu-baseline]
+                  [--form persistent|plain] [--no-cpu-baseline] [--no-adjoint]
+                  [--plain-steps N] [--check M]
 """
 from __future__ import annotations
 
@@ -72,7 +76,20 @@ def main():
     ap.add_argument("--form", default="persistent", choices=["persistent", "plain"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", type=int, default=2000, help="mixtures checked against the oracle")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.ones(2 ** 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(mixtures are independent: a multi-GPU run shards them with no exchange)",
@@ -130,6 +147,35 @@ def main():
         "status_counts": {k: int(((g["status"].astype(np.int64) & 0xffff) & v != 0).sum())
                           for k, v in _capi.ST.items()},
     }
+    # forward + adjoint: forward keeping the factor, then the implicit-function
+    # VJP with seeded N(0,1) cotangents and the batch-reduced k gradient
+    if not args.no_adjoint:
+        gb, gx, gy = (torch.as_tensor(a, dtype=torch.float64, device=dev)
+                      for a in workloads.cotangents(77, w.n, w.nc))
+        fo = api.flash(z, T, P, Tc, Pc, om, kij, keep_factor=True)
+        api.flash_backward(z, T, P, Tc, Pc, om, kij, fo, gb, gx, gy)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            api.flash(z, T, P, Tc, Pc, om, kij, keep_factor=True, out=fo)
+            bw = api.flash_backward(z, T, P, Tc, Pc, om, kij, fo, gb, gx, gy)
+        torch.cuda.synchronize()
+        wall_a = time.perf_counter() - t1
+        rec["fwd_adjoint"] = {"value": w.n * args.steps / wall_a, "unit": "flashes/s",
+                              "ms_per_step": wall_a * 1e3 / args.steps,
+                              "nan_grad_frac": float(torch.isnan(bw[1]).double().mean().item())}
+    if args.plain_steps > 0:
+        api.flash(z, T, P, Tc, Pc, om, kij, form=_capi.FORM_PLAIN, out=out)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            api.flash(z, T, P, Tc, Pc, om, kij, form=_capi.FORM_PLAIN, out=out)
+        torch.cuda.synchronize()
+        wall_p = time.perf_counter() - t2
+        rec["plain_form"] = {"value": w.n * args.plain_steps / wall_p, "unit": "flashes/s",
+                             "ms_per_step": wall_p * 1e3 / args.plain_steps,
+                             "persistent_speedup": (w.n * args.plain_steps / wall_p) and
+                             value / (w.n * args.plain_steps / wall_p)}
     if args.check > 0:
         import oracle
         sys.path.insert(0, os.path.join(ROOT, "tests"))

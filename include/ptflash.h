@@ -167,8 +167,11 @@ int ptflash_flash(const ptflash_problem *prob, const ptflash_options *opt,
  * symmetric: entry (i,j) is the derivative for a symmetric perturbation of
  * k_ij = k_ji, split equally between (i,j) and (j,i).  Single-phase mixtures
  * give g_z = (g_x + g_y) projected through the normalisation, g_T = g_P = 0
- * and zero k gradient.  Mixtures whose forward status has SPLIT_UNCONV or
- * STEP_CAP get NaN gradients. */
+ * and zero k gradient.  Mixtures whose forward status has INVALID,
+ * SPLIT_UNCONV or STEP_CAP get NaN gradients (and contribute nothing to a
+ * reduced k gradient).  The sum over mixtures is deterministic (fixed order).
+ * `workspace` must hold ptflash_backward_workspace_bytes() bytes (256-byte
+ * aligned). */
 int ptflash_flash_backward(const ptflash_problem *prob, const ptflash_options *opt,
                            const ptflash_result *fwd, const double *g_beta,
                            const double *g_x, const double *g_y, double *g_z,

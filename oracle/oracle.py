@@ -57,7 +57,7 @@ def lib():
             L.orc_split_residual.restype = C.c_double
             L.orc_ninfo.restype = C.c_int
             L.orc_flash_jacobian.argtypes = [C.c_int32, _D, C.c_double, C.c_double, _D, _D, _D,
-                                             _D, C.c_double, _D, _D]
+                                             _D, C.c_double, _D, C.c_double, _D]
             L.orc_flash_jacobian.restype = C.c_int
             L.orc_flash_batch.argtypes = [C.c_int64, C.c_int32, _D, _D, _D, _D, _D, _D, _D,
                                           C.c_int32, C.POINTER(OrcOpts), C.c_void_p, _D, _D,
@@ -159,16 +159,17 @@ def flash(w, opts: OrcOpts | None = None, threads: int | None = None, **kw):
     return dict(label=label, beta=beta, x=x, y=y, min_tpd=mtpd, info=info)
 
 
-def flash_jacobian(Tc, Pc, omega, kij, z, T, P, beta, y):
+def flash_jacobian(Tc, Pc, omega, kij, z, T, P, beta, y, hrel=1e-3):
     """Jacobian of (beta, x, y) of a converged two-phase result with respect
     to p = (z_raw[nc], T, P, k_ab for a < b), by the implicit function
-    theorem on the equal-fugacity system (finite-difference partials)."""
+    theorem on the equal-fugacity system (fourth-order finite-difference
+    partials with relative step hrel)."""
     Tc, Pc, omega, kij, z, y = map(_f64, (Tc, Pc, omega, kij, z, y))
     nc = len(z)
     npar = nc + 2 + nc * (nc - 1) // 2
     J = np.zeros((1 + 2 * nc, npar))
     rc = lib().orc_flash_jacobian(nc, _p(z), T, P, _p(Tc), _p(Pc), _p(omega), _p(kij),
-                                  float(beta), _p(y), _p(J))
+                                  float(beta), _p(y), float(hrel), _p(J))
     if rc != 0:
         raise RuntimeError("singular split Jacobian")
     return J

@@ -1029,8 +1029,9 @@ double orc_split_residual(int32_t nc, const double *Tc, const double *Pc,
  * x = (z~ - u) / sum(z~ - u), z~ = z_raw / sum z_raw; the outputs are
  * o = (beta = sum u, x, y).  By the implicit function theorem
  * du/dp = -(dr/du)^-1 dr/dp.  The partial Jacobians dr/du and dr/d(z~, T,
- * P, k) are central differences (steps of 1e-5 relative to the smallest
- * quantity they move: u_j and the liquid moles z~ - u for u and z~); dr/dz
+ * P, k) are fourth-order central differences (f(-2h), f(-h), f(h), f(2h);
+ * steps of hrel relative to the smallest quantity they move: u_j and the
+ * liquid moles z~ - u for u and z~); dr/dz
  * follows from dr/dz~ through the normalisation; the systems are solved by
  * Gaussian elimination; the outputs are differentiated in closed form:
  *   d beta = sum du, dy = (du - y d beta)/beta,
@@ -1051,7 +1052,8 @@ static void orc_res_zt(int nc, const double *u, const double *zt, double T, doub
  * singular. */
 int orc_flash_jacobian(int32_t nc, const double *zraw, double T, double P,
                        const double *Tc, const double *Pc, const double *omega,
-                       const double *kij, double beta, const double *y, double *J)
+                       const double *kij, double beta, const double *y, double hrel,
+                       double *J)
 {
     int np = nc + 2 + nc * (nc - 1) / 2, no = 1 + 2 * nc;
     double u[ORC_NCMAX], zt[ORC_NCMAX], s = 0.0, nlmin = INFINITY;
@@ -1063,20 +1065,27 @@ int orc_flash_jacobian(int32_t nc, const double *zraw, double T, double P,
         u[i] = beta * y[i];
         nlmin = fmin(nlmin, zt[i] - u[i]);
     }
+    double r2p[ORC_NCMAX], r2m[ORC_NCMAX];
     for (int j = 0; j < nc; ++j) {
-        double h = 1e-5 * fmin(u[j], zt[j] - u[j]);
+        double h = hrel * fmin(u[j], zt[j] - u[j]);
         memcpy(ut, u, sizeof(double) * nc);
         ut[j] = u[j] + h; orc_res_zt(nc, ut, zt, T, P, Tc, Pc, omega, kij, rp);
         ut[j] = u[j] - h; orc_res_zt(nc, ut, zt, T, P, Tc, Pc, omega, kij, rm);
-        for (int i = 0; i < nc; ++i) Ju[i * nc + j] = (rp[i] - rm[i]) / (2.0 * h);
+        ut[j] = u[j] + 2.0 * h; orc_res_zt(nc, ut, zt, T, P, Tc, Pc, omega, kij, r2p);
+        ut[j] = u[j] - 2.0 * h; orc_res_zt(nc, ut, zt, T, P, Tc, Pc, omega, kij, r2m);
+        for (int i = 0; i < nc; ++i)
+            Ju[i * nc + j] = (8.0 * (rp[i] - rm[i]) - (r2p[i] - r2m[i])) / (12.0 * h);
     }
     /* dr/dz~_k */
     for (int k = 0; k < nc; ++k) {
-        double h = 1e-5 * fmin(zt[k] - u[k], nlmin * 1e3);
+        double h = hrel * fmin(zt[k] - u[k], nlmin * 1e3);
         memcpy(zp, zt, sizeof(double) * nc);
         zp[k] = zt[k] + h; orc_res_zt(nc, u, zp, T, P, Tc, Pc, omega, kij, rp);
         zp[k] = zt[k] - h; orc_res_zt(nc, u, zp, T, P, Tc, Pc, omega, kij, rm);
-        for (int i = 0; i < nc; ++i) Jz[i * nc + k] = (rp[i] - rm[i]) / (2.0 * h);
+        zp[k] = zt[k] + 2.0 * h; orc_res_zt(nc, u, zp, T, P, Tc, Pc, omega, kij, r2p);
+        zp[k] = zt[k] - 2.0 * h; orc_res_zt(nc, u, zp, T, P, Tc, Pc, omega, kij, r2m);
+        for (int i = 0; i < nc; ++i)
+            Jz[i * nc + k] = (8.0 * (rp[i] - rm[i]) - (r2p[i] - r2m[i])) / (12.0 * h);
     }
     double k2[ORC_NCMAX * ORC_NCMAX], drp[ORC_NCMAX], du[ORC_NCMAX], dzt[ORC_NCMAX];
     double M[ORC_NCMAX * ORC_NCMAX];
@@ -1092,23 +1101,29 @@ int orc_flash_jacobian(int32_t nc, const double *zraw, double T, double P,
                 drp[i] = a;
             }
         } else if (q == nc || q == nc + 1) {
-            double h = 1e-5 * (q == nc ? T : P);
-            double Tp = T + (q == nc ? h : 0.0), Pp = P + (q == nc + 1 ? h : 0.0);
-            double Tm = T - (q == nc ? h : 0.0), Pm = P - (q == nc + 1 ? h : 0.0);
-            orc_res_zt(nc, u, zt, Tp, Pp, Tc, Pc, omega, kij, rp);
-            orc_res_zt(nc, u, zt, Tm, Pm, Tc, Pc, omega, kij, rm);
-            for (int i = 0; i < nc; ++i) drp[i] = (rp[i] - rm[i]) / (2.0 * h);
+            double h = hrel * (q == nc ? T : P);
+            double dT = q == nc ? h : 0.0, dP = q == nc + 1 ? h : 0.0;
+            orc_res_zt(nc, u, zt, T + dT, P + dP, Tc, Pc, omega, kij, rp);
+            orc_res_zt(nc, u, zt, T - dT, P - dP, Tc, Pc, omega, kij, rm);
+            orc_res_zt(nc, u, zt, T + 2.0 * dT, P + 2.0 * dP, Tc, Pc, omega, kij, r2p);
+            orc_res_zt(nc, u, zt, T - 2.0 * dT, P - 2.0 * dP, Tc, Pc, omega, kij, r2m);
+            for (int i = 0; i < nc; ++i)
+                drp[i] = (8.0 * (rp[i] - rm[i]) - (r2p[i] - r2m[i])) / (12.0 * h);
         } else {
             /* symmetric perturbation of k_ab = k_ba */
             if (q == nc + 2) { pa = 0; pb = 1; }
             else if (++pb == nc) { ++pa; pb = pa + 1; }
-            double h = 1e-5;
-            memcpy(k2, kij, sizeof(double) * nc * nc);
-            k2[pa * nc + pb] += h; k2[pb * nc + pa] += h;
-            orc_res_zt(nc, u, zt, T, P, Tc, Pc, omega, k2, rp);
-            k2[pa * nc + pb] -= 2.0 * h; k2[pb * nc + pa] -= 2.0 * h;
-            orc_res_zt(nc, u, zt, T, P, Tc, Pc, omega, k2, rm);
-            for (int i = 0; i < nc; ++i) drp[i] = (rp[i] - rm[i]) / (2.0 * h);
+            double h = hrel;
+            const double steps[4] = {h, -h, 2.0 * h, -2.0 * h};
+            double *outs[4] = {rp, rm, r2p, r2m};
+            for (int t = 0; t < 4; ++t) {
+                memcpy(k2, kij, sizeof(double) * nc * nc);
+                k2[pa * nc + pb] += steps[t];
+                k2[pb * nc + pa] += steps[t];
+                orc_res_zt(nc, u, zt, T, P, Tc, Pc, omega, k2, outs[t]);
+            }
+            for (int i = 0; i < nc; ++i)
+                drp[i] = (8.0 * (rp[i] - rm[i]) - (r2p[i] - r2m[i])) / (12.0 * h);
         }
         for (int i = 0; i < nc; ++i) du[i] = -drp[i];
         memcpy(M, Ju, sizeof(double) * nc * nc);

@@ -106,3 +106,65 @@ def eval_phase(c, T, P, Tc, Pc, omega, kij, *, derivs: bool = True, stream=None)
                                         _ptr(phi), _stream_handle(stream))
     _capi.check(rc, "ptflash_eval_phase")
     return lnphi, Z, phi
+
+
+def flash_backward(z, T, P, Tc, Pc, omega, kij, fwd: FlashResult, g_beta, g_x, g_y, *,
+                   kij_reduce: bool = True, stream=None):
+    """Vector-Jacobian product of a forward result computed with
+    keep_factor=True: returns (g_z, g_T, g_P, g_kij).  g_kij is (nc, nc)
+    summed over mixtures when kij_reduce, else (n, nc, nc)."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    z, T, P = _f64(z, dev), _f64(T, dev), _f64(P, dev)
+    Tc, Pc, omega, kij = (_f64(a, dev) for a in (Tc, Pc, omega, kij))
+    g_beta, g_x, g_y = _f64(g_beta, dev), _f64(g_x, dev), _f64(g_y, dev)
+    if fwd.factor is None:
+        raise ValueError("the forward result holds no factor (run flash with keep_factor=True)")
+    n, nc = z.shape
+    prob = make_problem(z, T, P, Tc, Pc, omega, kij)
+    o = _capi.default_options()
+    res = _capi.Result(label=_ptr(fwd.label).value, beta=_ptr(fwd.beta).value,
+                       x=_ptr(fwd.x).value, y=_ptr(fwd.y).value, iters=_ptr(fwd.iters).value,
+                       status=_ptr(fwd.status).value, flops=_ptr(fwd.flops).value,
+                       factor=_ptr(fwd.factor).value)
+    gz = torch.empty((n, nc), dtype=torch.float64, device=dev)
+    gT = torch.empty(n, dtype=torch.float64, device=dev)
+    gP = torch.empty(n, dtype=torch.float64, device=dev)
+    gk = torch.empty((nc, nc) if kij_reduce else (n, nc, nc), dtype=torch.float64, device=dev)
+    L = _capi.lib()
+    ws_bytes = L.ptflash_backward_workspace_bytes(C.byref(prob), int(kij_reduce))
+    ws = _workspace(ws_bytes, dev)
+    rc = L.ptflash_flash_backward(C.byref(prob), C.byref(o), C.byref(res), _ptr(g_beta),
+                                  _ptr(g_x), _ptr(g_y), _ptr(gz), _ptr(gT), _ptr(gP), _ptr(gk),
+                                  int(kij_reduce), _ptr(ws), ws_bytes, _stream_handle(stream))
+    _capi.check(rc, "ptflash_flash_backward")
+    gz._keepalive = (ws, z, T, P, Tc, Pc, omega, kij, g_beta, g_x, g_y)
+    return gz, gT, gP, gk
+
+
+class PTFlashFunction(torch.autograd.Function):
+    """(z, T, P, kij) -> (beta, x, y, label, status) with the implicit-function
+    adjoint in backward; Tc, Pc, omega are constants.  label and status are
+    not differentiable."""
+
+    @staticmethod
+    def forward(ctx, z, T, P, kij, Tc, Pc, omega):
+        r = flash(z, T, P, Tc, Pc, omega, kij, keep_factor=True)
+        ctx.save_for_backward(z, T, P, kij, Tc, Pc, omega)
+        ctx.fwd = r
+        ctx.mark_non_differentiable(r.label, r.status)
+        return r.beta, r.x, r.y, r.label, r.status
+
+    @staticmethod
+    def backward(ctx, g_beta, g_x, g_y, _gl, _gs):
+        z, T, P, kij, Tc, Pc, omega = ctx.saved_tensors
+        r = ctx.fwd
+        zeros = lambda t, g: torch.zeros_like(t) if g is None else g
+        gz, gT, gP, gk = flash_backward(z, T, P, Tc, Pc, omega, kij, r,
+                                        zeros(r.beta, g_beta), zeros(r.x, g_x),
+                                        zeros(r.y, g_y), kij_reduce=True)
+        return gz, gT, gP, gk, None, None, None
+
+
+def flash_autograd(z, T, P, kij, Tc, Pc, omega):
+    """Differentiable flash: returns (beta, x, y, label, status)."""
+    return PTFlashFunction.apply(z, T, P, kij, Tc, Pc, omega)

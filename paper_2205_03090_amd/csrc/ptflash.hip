@@ -13,6 +13,7 @@
 
 #include "ptflash.h"
 #include "flash_lane.hpp"
+#include "adjoint_device.hpp"
 
 namespace ptf {
 
@@ -145,6 +146,165 @@ plain_compact(const Lane<NC> *__restrict__ states, const int32_t *__restrict__ i
     if ((states[m].stage == stage) == (keep_equal != 0)) {
         const unsigned long long j = atomicAdd(outc, 1ull);
         out[j] = m;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Backward (implicit function theorem on the converged split)
+// ---------------------------------------------------------------------------
+
+struct BwdArgs {
+    int64_t n;
+    const double *z, *T, *P;
+    const int8_t *label;
+    const double *beta, *x, *y, *factor;
+    const uint16_t *status;
+    const double *gb, *gx, *gy;
+    double *gz, *gT, *gP;
+    double *gk;        // n*nc*nc (per mixture) or NULL when reduced
+    double *kpart;     // npair*n contributions (pair-major) when reduced
+};
+
+template <int NC>
+__global__ void __launch_bounds__(kBlock)
+flash_backward_kernel(BwdArgs a, const double *__restrict__ Tc, const double *__restrict__ Pc,
+                      const double *__restrict__ om, const double *__restrict__ K)
+{
+    constexpr int NP = Tri<NC>::N;
+    constexpr int NQ = NC * (NC - 1) / 2;
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= a.n) return;
+    double zt[NC], s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NC; ++i) { zt[i] = a.z[m * NC + i]; s += zt[i]; }
+#pragma unroll
+    for (int i = 0; i < NC; ++i) zt[i] /= s;
+    const uint16_t st = a.status ? a.status[m] : (uint16_t)0;
+    double ztb[NC], gT = 0.0, gP = 0.0;
+    double gkq[NQ > 0 ? NQ : 1];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) gkq[q] = 0.0;
+    bool bad = (st & (kStInvalid | kStSplitUnconv | kStStepCap)) != 0;
+    if (!bad && a.label[m] == 1) {
+        const double T = a.T[m], P = a.P[m], beta = a.beta[m];
+        double x[NC], y[NC], gx[NC], gy[NC];
+        double gxx = 0.0, gyy = 0.0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            x[i] = a.x[m * NC + i];
+            y[i] = a.y[m * NC + i];
+            gx[i] = a.gx[m * NC + i];
+            gy[i] = a.gy[m * NC + i];
+            gxx += gx[i] * x[i];
+            gyy += gy[i] * y[i];
+        }
+        const double gb = a.gb[m];
+        // u_bar = (do/du)^T o_bar for o = (beta = sum u, y = u/beta,
+        // x = (z~ - u)/(1 - beta))
+        double lam[NC];
+        const double ib = 1.0 / beta, il = 1.0 / (1.0 - beta);
+#pragma unroll
+        for (int j = 0; j < NC; ++j) lam[j] = gb + (gy[j] - gyy) * ib - (gx[j] - gxx) * il;
+        // H~ lambda = u_bar with the forward's factor H~ = L L^T
+        double Lf[NP], dinv[NC], tmp[NC];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) Lf[k] = a.factor[m * NP + k];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) dinv[i] = 1.0 / Lf[tri(i, i)];
+        lower_solve<NC>(tmp, Lf, dinv, lam);
+        upper_solve<NC>(lam, Lf, dinv, tmp);
+        bad = !isfinite(lam[0]);
+        // phase data at the solution
+        Eos<NC> e;
+        eos_setup<NC>(e, Tc, Pc, om, T, P);
+        uint32_t fl = 0;
+        Phase<NC> oL, oV;
+        phase_eval<NC>(oL, e, K, x, fl);
+        double Phi[NP];
+        phase_derivs<NC>(Phi, oL, e, K, fl);
+        // z~_bar_j = [gx_j + lambda_j/x_j - sum lambda + (Phi^L lambda)_j]/(1 - beta)
+        double sl = 0.0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) sl += lam[i];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            double pl = 0.0;
+#pragma unroll
+            for (int i = 0; i < NC; ++i) pl += Phi[i >= j ? tri(i, j) : tri(j, i)] * lam[i];
+            ztb[j] = (gx[j] + lam[j] / x[j] - sl + pl) * il;
+        }
+        PhaseGrad<NC> gL, gV;
+        phase_param_vjp<NC>(gL, oL, e, x, lam, K, Tc, om, T, P);
+        phase_eval<NC>(oV, e, K, y, fl);
+        phase_param_vjp<NC>(gV, oV, e, y, lam, K, Tc, om, T, P);
+        gT = -(gV.dT - gL.dT);
+        gP = -(gV.dP - gL.dP);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) gkq[q] = -(gV.dk[q] - gL.dk[q]);
+    } else if (!bad) {
+        // single phase: x = y = z~
+#pragma unroll
+        for (int i = 0; i < NC; ++i) ztb[i] = a.gx[m * NC + i] + a.gy[m * NC + i];
+    }
+    if (bad) {
+        const double nan = __builtin_nan("");
+#pragma unroll
+        for (int i = 0; i < NC; ++i) ztb[i] = nan;
+        gT = gP = nan;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) gkq[q] = nan;
+    }
+    // through the normalisation z~ = z / sum z
+    double zz = 0.0;
+#pragma unroll
+    for (int i = 0; i < NC; ++i) zz += ztb[i] * zt[i];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) a.gz[m * NC + j] = (ztb[j] - zz) / s;
+    a.gT[m] = gT;
+    a.gP[m] = gP;
+    if (a.gk) {
+        int q = 0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) a.gk[m * NC * NC + i * NC + i] = bad ? gT /* NaN */ : 0.0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i)
+#pragma unroll
+            for (int j = i + 1; j < NC; ++j, ++q) {
+                a.gk[m * NC * NC + i * NC + j] = 0.5 * gkq[q];
+                a.gk[m * NC * NC + j * NC + i] = 0.5 * gkq[q];
+            }
+    }
+    if (a.kpart) {
+        // unconverged mixtures (NaN above) do not enter the batch sum
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) a.kpart[(int64_t)q * a.n + m] = bad ? 0.0 : gkq[q];
+    }
+}
+
+// Deterministic batch sum of the k contributions: one block per pair, each
+// thread sums a fixed strided subset in order, then a fixed tree in LDS.
+__global__ void __launch_bounds__(kBlock)
+reduce_pairs(const double *__restrict__ kpart, int64_t n, int nc, double *gk)
+{
+    __shared__ double red[kBlock];
+    const int q = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t m = threadIdx.x; m < n; m += kBlock) acc += kpart[(int64_t)q * n + m];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        // pair index -> (i, j), i < j
+        int i = 0, r = q;
+        while (r >= nc - 1 - i) { r -= nc - 1 - i; ++i; }
+        const int j = i + 1 + r;
+        gk[i * nc + j] = 0.5 * red[0];
+        gk[j * nc + i] = 0.5 * red[0];
+        if (q == 0)
+            for (int d = 0; d < nc; ++d) gk[d * nc + d] = 0.0;
     }
 }
 
@@ -341,6 +501,17 @@ struct PlainWsF {
 };
 
 template <int NC>
+struct BackwardF {
+    static int run(const BwdArgs &b, const ptflash_problem *p, hipStream_t s)
+    {
+        const unsigned nb = (unsigned)((p->n + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(flash_backward_kernel<NC>, dim3(nb), dim3(kBlock), 0, s, b, p->Tc,
+                           p->Pc, p->omega, p->kij);
+        return hipGetLastError() == hipSuccess ? PTFLASH_OK : PTFLASH_EHIP;
+    }
+};
+
+template <int NC>
 struct EvalF {
     static int run(int64_t n, const double *c, const double *T, const double *P,
                    const double *Tc, const double *Pc, const double *om, const double *K,
@@ -439,8 +610,9 @@ int ptflash_eval_phase(int64_t n, int32_t nc, const double *c, const double *T,
 
 size_t ptflash_backward_workspace_bytes(const ptflash_problem *p, int32_t kij_reduce)
 {
-    (void)kij_reduce;
     if (!problem_ok(p)) return 0;
+    const int64_t npair = (int64_t)p->nc * (p->nc - 1) / 2;
+    if (kij_reduce) return 256 + align256((size_t)npair * (size_t)p->n * sizeof(double));
     return 256;
 }
 
@@ -450,9 +622,45 @@ int ptflash_flash_backward(const ptflash_problem *p, const ptflash_options *o,
                            double *g_kij, int32_t kij_reduce, void *ws, size_t ws_bytes,
                            hipStream_t s)
 {
-    (void)p; (void)o; (void)fwd; (void)g_beta; (void)g_x; (void)g_y; (void)g_z; (void)g_T;
-    (void)g_P; (void)g_kij; (void)kij_reduce; (void)ws; (void)ws_bytes; (void)s;
-    return PTFLASH_EUNSUPPORTED;
+    (void)o;
+    if (!problem_ok(p) || !fwd) return PTFLASH_EINVAL;
+    if (p->nc < kMinNc || p->nc > kMaxNc) return PTFLASH_EUNSUPPORTED;
+    if (p->props_per_mixture != 0) return PTFLASH_EUNSUPPORTED;
+    if (p->n == 0) return PTFLASH_OK;
+    if (!fwd->label || !fwd->beta || !fwd->x || !fwd->y || !fwd->factor) return PTFLASH_EINVAL;
+    if (!g_beta || !g_x || !g_y || !g_z || !g_T || !g_P || !g_kij) return PTFLASH_EINVAL;
+    if (kij_reduce != 0 && kij_reduce != 1) return PTFLASH_EINVAL;
+    const size_t need = ptflash_backward_workspace_bytes(p, kij_reduce);
+    if (ws_bytes < need || (need > 0 && !ws)) return PTFLASH_EWORKSPACE;
+    if (((uintptr_t)ws & 255u) != 0) return PTFLASH_EINVAL;
+    BwdArgs b;
+    b.n = p->n;
+    b.z = p->z;
+    b.T = p->T;
+    b.P = p->P;
+    b.label = fwd->label;
+    b.beta = fwd->beta;
+    b.x = fwd->x;
+    b.y = fwd->y;
+    b.factor = fwd->factor;
+    b.status = fwd->status;
+    b.gb = g_beta;
+    b.gx = g_x;
+    b.gy = g_y;
+    b.gz = g_z;
+    b.gT = g_T;
+    b.gP = g_P;
+    b.gk = kij_reduce ? nullptr : g_kij;
+    b.kpart = kij_reduce ? (double *)((char *)ws + 256) : nullptr;
+    int rc = Dispatch<BackwardF>::run(p->nc, b, p, s);
+    if (rc) return rc;
+    if (kij_reduce) {
+        const int npair = p->nc * (p->nc - 1) / 2;
+        hipLaunchKernelGGL(reduce_pairs, dim3(npair), dim3(kBlock), 0, s, b.kpart, p->n, p->nc,
+                           g_kij);
+        if (hipGetLastError() != hipSuccess) return PTFLASH_EHIP;
+    }
+    return PTFLASH_OK;
 }
 
 const char *ptflash_strerror(int code)
