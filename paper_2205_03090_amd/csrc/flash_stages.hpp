@@ -1,0 +1,1000 @@
+// flash_stages.hpp -- the flash as a pipeline of stages, each a work item
+// type with begin() (cheap: load the item's state) and step() (one iteration
+// of the stage; every SRK phase evaluation of the stage goes through the same
+// call sites, so lanes of a wavefront evaluate the equation of state together).
+//
+// Stages (Sec. 2.2.3 strategy; Sec. 3 vectorisation with a barrier per stage):
+//   Pre    one per mixture: feed evaluation d = ln z + ln phi(z), Wilson K,
+//          three phase-split substitutions, triage into cases 1/2/3
+//   SaSs   one per stability trial (V or L): successive substitution with
+//          dominant-eigenvalue acceleration (Sec. 2.2.1)
+//   SaTr   one per trial that needed more: trust region in beta = 2 sqrt(W)
+//          (Appendix B.1)
+//   SaFin  one per analysed mixture: label decision and K re-estimate
+//   SpSs   one per unstable mixture: split substitution (Sec. 2.2.2)
+//   SpNt   one per split: trust region on G (Appendix B.2), Newton
+//          refinement, outputs
+// Items of one stage never depend on each other; a stage starts when the
+// previous one has finished (kernel order on the stream).
+//
+// Readings of the paper used here (identical in the CPU oracle):
+//   * tm carries Michelsen's leading 1 (tm = 0 at the trivial point);
+//   * Delta G of the triage is (1-theta) tpd(x) + theta tpd(y);
+//   * a trial is unstable when tm < -eps_tm;
+//   * dominant-eigenvalue acceleration at every dem_every-th substitution
+//     update u >= 2: lambda = (s_u.s_u)/(s_{u-1}.s_u), extension by
+//     s_u lambda/(1 - lambda) when 0 < lambda < 1, kept only if the
+//     extrapolated point lowers the objective (tm, or G per unit feed),
+//     otherwise replaced by the plain update (not counted as an iteration);
+//   * the trials start from the Wilson K, the initial substitutions stop at
+//     the first Rachford-Rice root outside (0,1) (case 1), and a case-3 split
+//     continues from the latest K with a fresh substitution budget;
+//   * the split trust region is scaled: u = D^(1/2) dn with
+//     D = diag(z/(x y)), the paper's shift matrix;
+//   * the converged split is refined by Newton steps until max |dn| is
+//     below tol_polish, and y is chosen as the phase with the larger Z.
+#pragma once
+
+#include "srk_device.hpp"
+
+namespace ptf {
+
+// status bits (same values as the public header)
+constexpr uint32_t kStInvalid = 0x0001u, kStShortcut = 0x0002u, kStSaRan = 0x0004u,
+                   kStSaUnconv = 0x0008u, kStSplitTr = 0x0010u, kStSplitUnconv = 0x0020u,
+                   kStSplitTrivial = 0x0040u, kStSplitFailed = 0x0080u,
+                   kStRrNoRoot = 0x0100u, kStSwapped = 0x0200u, kStStepCap = 0x0400u;
+
+// A split whose smaller phase holds less than this fraction of the feed is
+// reported as failed (single phase).
+constexpr double kMinPhase = 1e-10;
+
+// Per-stage guard on the number of steps of one item (every stage is bounded
+// by its iteration caps; this only guarantees termination).
+constexpr int kStepGuard = 96;
+
+// Per-mixture record kept in the workspace between stages.
+template <int NC>
+struct MixRec {
+    double s[NC], b[NC];   // EOS constants at (T, P): sqrt(A_i), B_i
+    double lnz[NC];        // ln of the normalised feed
+    double d[NC];          // ln z + ln phi(z)
+    double lkw[NC];        // Wilson ln K
+    double lk[NC];         // split ln K (Pre case 3, SaFin), then n^V (SpSs -> SpNt)
+    double lw[2][NC];      // ln W of the stability trials (start of SaTr, final)
+    double tm[2];          // final tm of the trials
+    double theta;          // Rachford-Rice warm start
+    uint32_t status;
+    uint32_t fl;           // algorithmic flops of the mixture's sequential stages
+    uint32_t tfl[2];       // flops of each trial
+    uint32_t tst[2];       // status bits of each trial
+    int16_t it[8];
+};
+
+// Kernel arguments shared by every stage.
+struct FlashArgs {
+    int64_t n;
+    const double *z, *T, *P;
+    int max_pre_ss, max_ss, max_tr_sa, max_tr_split, max_polish, dem_every;
+    int keep_factor;
+    double tol_sa_ss, tol_sa_tr, tol_split_ss, tol_split_tr, tol_polish, eps_tm;
+    int8_t *label;
+    double *beta, *x, *y;
+    int16_t *iters;
+    uint16_t *status;
+    uint32_t *flops;
+    double *factor;
+};
+
+// Work lists: ids (mixture m, or trial 2m + t) and their counts.
+enum ListId : int { L_SA = 0, L_SATR = 1, L_SAFIN = 2, L_SPLIT = 3, L_NT = 4, L_COUNT = 5 };
+
+struct Lists {
+    uint32_t *ids[L_COUNT];
+    unsigned long long *count;   // L_COUNT counters
+};
+
+// Read-only shared component set (restrict pointers: compile-time indexed
+// loads become wave-uniform scalar loads).
+struct Props {
+    const double *__restrict__ Tc;
+    const double *__restrict__ Pc;
+    const double *__restrict__ om;
+    const double *__restrict__ K;
+};
+
+template <int NC>
+struct Ctx {
+    FlashArgs a;
+    Props pr;
+    MixRec<NC> *rec;
+    Lists L;
+};
+
+__device__ __forceinline__ void push(const Lists &L, int list, uint32_t id)
+{
+    const unsigned long long k = atomicAdd(&L.count[list], 1ull);
+    L.ids[list][k] = id;
+}
+
+// ---------------------------------------------------------------------------
+// Shared helpers
+// ---------------------------------------------------------------------------
+
+template <int NC>
+__device__ __forceinline__ void load_z(double (&z)[NC], const FlashArgs &a, int64_t m)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NC; ++i) { z[i] = a.z[m * NC + i]; s += z[i]; }
+#pragma unroll
+    for (int i = 0; i < NC; ++i) z[i] = z[i] / s;
+}
+
+template <int NC>
+__device__ __forceinline__ void write_outputs_single(const Ctx<NC> &c, int64_t m,
+                                                     const double (&z)[NC], uint32_t status,
+                                                     uint32_t fl, const int16_t (&it)[8])
+{
+    const FlashArgs &a = c.a;
+    a.label[m] = 0;
+    a.beta[m] = -1.0;
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+        a.x[m * NC + i] = z[i];
+        a.y[m * NC + i] = z[i];
+    }
+    if (a.iters) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) a.iters[m * 8 + k] = it[k];
+    }
+    if (a.status) a.status[m] = (uint16_t)status;
+    if (a.flops) a.flops[m] = fl;
+}
+
+template <int NC>
+__device__ __forceinline__ void load_it(int16_t (&it)[8], const MixRec<NC> &r)
+{
+#pragma unroll
+    for (int k = 0; k < 8; ++k) it[k] = r.it[k];
+}
+
+// K -> Rachford-Rice -> normalised x, y (x_i = z_i/(1 + th(K_i - 1)),
+// y_i = K_i x_i).  False when no root exists.
+template <int NC>
+__device__ __forceinline__ bool xy_from_lnk(double (&x)[NC], double (&y)[NC],
+                                            const double (&lnk)[NC], const double (&z)[NC],
+                                            double &theta, uint32_t &fl)
+{
+    double K[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) K[i] = exp(lnk[i]);
+    fl += NC;
+    if (!rr_solve<NC>(z, K, theta, fl)) return false;
+    double sx = 0.0, sy = 0.0;
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+        x[i] = z[i] / (1.0 + theta * (K[i] - 1.0));
+        y[i] = K[i] * x[i];
+        sx += x[i];
+        sy += y[i];
+    }
+    const double ix = 1.0 / sx, iy = 1.0 / sy;
+#pragma unroll
+    for (int i = 0; i < NC; ++i) { x[i] *= ix; y[i] *= iy; }
+    fl += 8 * NC + 2;
+    return true;
+}
+
+// One substitution update with acceleration: v += s (1 + ext); returns ext.
+template <int NC>
+__device__ __forceinline__ double ss_update(double (&v)[NC], double (&prev)[NC],
+                                            const double (&s)[NC], int u, int dem, uint32_t &fl)
+{
+    double ext = 0.0;
+    if (dem > 0 && u >= 2 && (u % dem) == 0) {
+        double num = 0.0, den = 0.0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) { num += s[i] * s[i]; den += prev[i] * s[i]; }
+        const double lam = num / den;
+        if (lam > 0.0 && lam < 1.0) ext = lam / (1.0 - lam);
+        fl += 4 * NC + 3;
+    }
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+        v[i] += s[i] + ext * s[i];
+        prev[i] = s[i];
+    }
+    fl += 3 * NC;
+    return ext;
+}
+
+// ---------------------------------------------------------------------------
+// Pre: feed, Wilson, three substitutions, triage (Sec. 2.2.3)
+// ---------------------------------------------------------------------------
+template <int NC>
+struct PreItem {
+    static constexpr int LIST = -1;   // input: mixtures 0..n-1
+    int64_t m;
+    double T, P;
+    double z[NC], d[NC], lk[NC];
+    Eos<NC> e;
+    double theta;
+    int phase;   // 0: feed evaluation pending; k >= 1: k-th substitution
+    int steps;
+    uint32_t fl;
+
+    __device__ __forceinline__ bool begin(const Ctx<NC> &c, uint32_t id)
+    {
+        const FlashArgs &a = c.a;
+        m = id;
+        T = a.T[m];
+        P = a.P[m];
+        fl = 0;
+        steps = 0;
+        phase = 0;
+        theta = 0.5;
+        bool ok = (T > 0.0) && (P > 0.0) && isfinite(T) && isfinite(P);
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            const double zi = a.z[m * NC + i];
+            ok = ok && (zi > 0.0) && isfinite(zi);
+            z[i] = zi;
+            s += zi;
+        }
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            ok = ok && (c.pr.Tc[i] > 0.0) && (c.pr.Pc[i] > 0.0) && isfinite(c.pr.om[i]);
+            ok = ok && (c.pr.K[i * NC + i] == 0.0);
+#pragma unroll
+            for (int j = 0; j < i; ++j) ok = ok && (c.pr.K[i * NC + j] == c.pr.K[j * NC + i]);
+        }
+        if (!ok) {
+            // invalid input: report the raw feed as a single phase
+            int16_t it[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            write_outputs_single<NC>(c, m, z, kStInvalid, 0, it);
+            return false;
+        }
+#pragma unroll
+        for (int i = 0; i < NC; ++i) z[i] = z[i] / s;
+        eos_setup<NC>(e, c.pr.Tc, c.pr.Pc, c.pr.om, T, P);
+        return true;
+    }
+
+    // stores what the later stages need and routes the mixture
+    __device__ __forceinline__ void route(const Ctx<NC> &c, bool to_split, uint32_t status,
+                                          const double (&lkw)[NC])
+    {
+        MixRec<NC> &r = c.rec[m];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            r.s[i] = e.s[i];
+            r.b[i] = e.b[i];
+            r.lnz[i] = log(z[i]);
+            r.d[i] = d[i];
+            r.lkw[i] = lkw[i];
+            r.lk[i] = lk[i];
+        }
+        fl += NC;
+        r.theta = theta;
+        r.status = status;
+        r.fl = fl;
+        r.tfl[0] = r.tfl[1] = 0;
+        r.tst[0] = r.tst[1] = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) r.it[k] = 0;
+        r.it[0] = (int16_t)(phase - 1 < 0 ? 0 : phase - 1);
+        if (to_split) {
+            push(c.L, L_SPLIT, (uint32_t)m);
+        } else {
+            push(c.L, L_SA, (uint32_t)(2 * m));
+            push(c.L, L_SA, (uint32_t)(2 * m + 1));
+            push(c.L, L_SAFIN, (uint32_t)m);
+        }
+    }
+
+    __device__ __forceinline__ void wilson(double (&lk_out)[NC], const Props &pr) const
+    {
+#pragma unroll
+        for (int i = 0; i < NC; ++i)
+            lk_out[i] = log(pr.Pc[i] / P) + kWilson * (1.0 + pr.om[i]) * (1.0 - pr.Tc[i] / T);
+    }
+
+    __device__ __forceinline__ bool step(const Ctx<NC> &c)
+    {
+        const FlashArgs &a = c.a;
+        double w0[NC], w1[NC];
+        bool e1 = true;
+        if (phase == 0) {
+#pragma unroll
+            for (int i = 0; i < NC; ++i) w0[i] = z[i];
+            e1 = false;
+        } else if (!(xy_from_lnk<NC>(w0, w1, lk, z, theta, fl) && theta > 0.0 && theta < 1.0)) {
+            // case 1: the Rachford-Rice root left (0,1)
+            double lkw[NC];
+            wilson(lkw, c.pr);
+            fl += 5 * NC;
+            route(c, false, kStSaRan, lkw);
+            return true;
+        }
+        Phase<NC> o;
+        phase_eval<NC>(o, e, c.pr.K, w0, fl);
+        double r0[NC];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) r0[i] = o.lnphi[i];
+        if (e1) phase_eval<NC>(o, e, c.pr.K, w1, fl);
+        if (phase == 0) {
+#pragma unroll
+            for (int i = 0; i < NC; ++i) d[i] = log(z[i]) + r0[i];
+            fl += 2 * NC;
+            wilson(lk, c.pr);
+            fl += 5 * NC;
+            phase = 1;
+            return false;
+        }
+#pragma unroll
+        for (int i = 0; i < NC; ++i) lk[i] = r0[i] - o.lnphi[i];
+        fl += NC;
+        ++phase;
+        if (phase - 1 < a.max_pre_ss && ++steps < kStepGuard) return false;
+        // triage (Sec. 2.2.3): tpd of the current liquid and vapour
+        double tx = 0.0, ty = 0.0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            tx += w0[i] * (log(w0[i]) + r0[i] - d[i]);
+            ty += w1[i] * (log(w1[i]) + o.lnphi[i] - d[i]);
+        }
+        const double dg = (1.0 - theta) * tx + theta * ty;
+        fl += 8 * NC + 3;
+        double lkw[NC];
+        wilson(lkw, c.pr);
+        fl += 5 * NC;
+        if (tx < -a.eps_tm || ty < -a.eps_tm || dg < -a.eps_tm) {
+            theta = 0.5;
+            route(c, true, kStShortcut, lkw);
+        } else {
+            route(c, false, kStSaRan, lkw);
+        }
+        return true;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// SaSs: successive substitution of one stability trial (Sec. 2.2.1, eq.
+// ss_analyser): ln W <- d - ln phi(W)
+// ---------------------------------------------------------------------------
+template <int NC>
+struct SaSsItem {
+    static constexpr int LIST = L_SA;
+    int64_t m;
+    int t;
+    double lw[NC], prev[NC], d[NC];
+    Eos<NC> e;
+    double tmb, ext;
+    bool dem;
+    int ss, steps;
+    uint32_t fl, st;
+
+    __device__ __forceinline__ bool begin(const Ctx<NC> &c, uint32_t id)
+    {
+        m = id >> 1;
+        t = (int)(id & 1u);
+        const MixRec<NC> &r = c.rec[m];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            e.s[i] = r.s[i];
+            e.b[i] = r.b[i];
+            d[i] = r.d[i];
+            lw[i] = t == 0 ? r.lnz[i] + r.lkw[i] : r.lnz[i] - r.lkw[i];
+        }
+        fl = 2 * NC;
+        st = 0;
+        ss = 0;
+        steps = 0;
+        dem = false;
+        return true;
+    }
+
+    __device__ __forceinline__ void done(const Ctx<NC> &c, double tm, bool to_tr)
+    {
+        MixRec<NC> &r = c.rec[m];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) r.lw[t][i] = lw[i];
+        r.tm[t] = tm;
+        r.it[t == 0 ? 1 : 3] = (int16_t)ss;
+        r.it[t == 0 ? 2 : 4] = 0;
+        r.tfl[t] = fl;
+        r.tst[t] = st;
+        if (to_tr) push(c.L, L_SATR, (uint32_t)(2 * m + t));
+    }
+
+    __device__ __forceinline__ bool step(const Ctx<NC> &c)
+    {
+        const FlashArgs &a = c.a;
+        double W[NC];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) W[i] = exp(lw[i]);
+        fl += NC;
+        Phase<NC> o;
+        phase_eval<NC>(o, e, c.pr.K, W, fl);
+        double grad[NC], tm = 1.0, gmax = 0.0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            grad[i] = lw[i] + o.lnphi[i] - d[i];
+            tm += W[i] * (grad[i] - 1.0);
+            gmax = fmax(gmax, fabs(grad[i]));
+        }
+        fl += 6 * NC;
+        if (tm < -a.eps_tm || gmax < a.tol_sa_ss) {
+            done(c, tm, false);
+            return true;
+        }
+        if (dem) {
+            // an extrapolated point is kept only if it lowers tm
+            dem = false;
+            if (!(tm < tmb)) {
+#pragma unroll
+                for (int i = 0; i < NC; ++i) lw[i] -= ext * prev[i];
+                if (++steps < kStepGuard) return false;
+            }
+        }
+        if (ss < a.max_ss && ++steps < kStepGuard) {
+            double s[NC];
+#pragma unroll
+            for (int i = 0; i < NC; ++i) s[i] = -grad[i];
+            ext = ss_update<NC>(lw, prev, s, ss + 1, a.dem_every, fl);
+            ++ss;
+            if (ext > 0.0) {
+                dem = true;
+                tmb = tm;
+            }
+            return false;
+        }
+        // substitution budget spent: continue with the trust region here
+        done(c, tm, true);
+        return true;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// SaTr: trust region of one trial in beta = 2 sqrt(W) (Appendix B.1,
+// eqs. tr_sa, analysis_grad, analysis_hess)
+// ---------------------------------------------------------------------------
+template <int NC>
+struct SaTrItem {
+    static constexpr int LIST = L_SATR;
+    static constexpr int NP = Tri<NC>::N;
+    int64_t m;
+    int t;
+    double lw[NC], lacc[NC], d[NC];
+    Eos<NC> e;
+    double rad, facc, pred, gacc;
+    bool pend;
+    int tr, steps;
+    uint32_t fl, st;
+
+    __device__ __forceinline__ bool begin(const Ctx<NC> &c, uint32_t id)
+    {
+        m = id >> 1;
+        t = (int)(id & 1u);
+        const MixRec<NC> &r = c.rec[m];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            e.s[i] = r.s[i];
+            e.b[i] = r.b[i];
+            d[i] = r.d[i];
+            lw[i] = r.lw[t][i];
+        }
+        fl = r.tfl[t];
+        st = r.tst[t];
+        rad = 0.0;
+        pend = false;
+        tr = 0;
+        steps = 0;
+        return true;
+    }
+
+    __device__ __forceinline__ void done(const Ctx<NC> &c, double tm)
+    {
+        MixRec<NC> &r = c.rec[m];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) r.lw[t][i] = lw[i];
+        r.tm[t] = tm;
+        r.it[t == 0 ? 2 : 4] = (int16_t)tr;
+        r.tfl[t] = fl;
+        r.tst[t] = st;
+    }
+
+    __device__ __forceinline__ bool step(const Ctx<NC> &c)
+    {
+        const FlashArgs &a = c.a;
+        double W[NC];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) W[i] = exp(lw[i]);
+        fl += NC;
+        Phase<NC> o;
+        phase_eval<NC>(o, e, c.pr.K, W, fl);
+        double F[NP], Hs[NP], dinv[NC];
+        phase_derivs<NC>(F, o, e, c.pr.K, fl);
+        double grad[NC], g[NC], tm = 1.0, sw = 0.0, gmax = 0.0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            grad[i] = lw[i] + o.lnphi[i] - d[i];
+            tm += W[i] * (grad[i] - 1.0);
+            sw += W[i];
+            g[i] = sqrt(W[i]) * grad[i];
+            gmax = fmax(gmax, fabs(g[i]));
+        }
+        fl += 9 * NC;
+        if (pend) {
+            pend = false;
+            bool accept;
+            double ratio = 1.0;
+            if (fabs(pred) < 1e-13) {
+                accept = gmax < gacc;
+            } else {
+                ratio = (tm - facc) / pred;
+                accept = (tm < facc) && ratio > 0.0;
+            }
+            if (!accept) {
+                rad *= 0.5;
+#pragma unroll
+                for (int i = 0; i < NC; ++i) lw[i] = lacc[i];
+                if (++steps < kStepGuard) return false;   // re-evaluate there
+                st |= kStSaUnconv;
+                done(c, facc);
+                return true;
+            }
+            if (ratio <= 0.25) rad *= 0.5;
+            else if (ratio >= 0.75) rad *= 2.0;
+        }
+        if (tm < -a.eps_tm || gmax < a.tol_sa_tr) {
+            done(c, tm);
+            return true;
+        }
+        if (tr >= a.max_tr_sa || ++steps >= kStepGuard) {
+            st |= kStSaUnconv;
+            done(c, tm);
+            return true;
+        }
+        // H_ij = delta_ij (1 + grad_i/2) + sqrt(c_i c_j) Phi_ij
+        double rc[NC];
+        const double isw = 1.0 / sw;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) rc[i] = sqrt(W[i] * isw);
+#pragma unroll
+        for (int i = 0; i < NC; ++i)
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                Hs[tri(i, j)] = rc[i] * rc[j] * F[tri(i, j)] + ((i == j) ? 1.0 + 0.5 * grad[i] : 0.0);
+        fl += 2 * NP + 4 * NC;
+        double u[NC];
+        bool eta0;
+        double pr = trust_step<NC>(u, rad, eta0, F, dinv, Hs, g, fl);
+        double amax = 1.0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            const double bi = 2.0 * sqrt(W[i]);
+            if (u[i] < 0.0) amax = fmin(amax, 0.99 * bi / -u[i]);
+        }
+        if (amax < 1.0) {
+            double gu = 0.0;
+#pragma unroll
+            for (int i = 0; i < NC; ++i) gu += g[i] * u[i];
+            pr = amax * gu + amax * amax * (pr - gu);
+        }
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            lacc[i] = lw[i];
+            lw[i] = 2.0 * log(sqrt(W[i]) + 0.5 * amax * u[i]);
+        }
+        fl += 6 * NC;
+        facc = tm;
+        gacc = gmax;
+        pred = pr;
+        pend = true;
+        ++tr;
+        return false;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// SaFin: label decision and K re-estimate (Sec. 2.2.1, last paragraph)
+// ---------------------------------------------------------------------------
+template <int NC>
+struct SaFinItem {
+    static constexpr int LIST = L_SAFIN;
+    int64_t m;
+
+    __device__ __forceinline__ bool begin(const Ctx<NC> &c, uint32_t id)
+    {
+        m = id;
+        return true;
+    }
+
+    __device__ __forceinline__ bool step(const Ctx<NC> &c)
+    {
+        MixRec<NC> &r = c.rec[m];
+        const double t0 = r.tm[0], t1 = r.tm[1];
+        const uint32_t status = r.status | r.tst[0] | r.tst[1];
+        uint32_t fl = r.fl + r.tfl[0] + r.tfl[1];
+        const bool unstable = (t0 < -c.a.eps_tm) || (t1 < -c.a.eps_tm);
+        if (!unstable) {
+            double z[NC];
+            load_z<NC>(z, c.a, m);
+            int16_t it[8];
+            load_it<NC>(it, r);
+            write_outputs_single<NC>(c, m, z, status, fl, it);
+            return true;
+        }
+        if (t1 < t0) {
+#pragma unroll
+            for (int i = 0; i < NC; ++i) r.lk[i] = r.lnz[i] - r.lw[1][i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < NC; ++i) r.lk[i] = r.lw[0][i] - r.lnz[i];
+        }
+        r.theta = 0.5;
+        r.status = status;
+        r.fl = fl + NC;
+        push(c.L, L_SPLIT, (uint32_t)m);
+        return true;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// SpSs: successive substitution of the split (Sec. 2.2.2)
+// ---------------------------------------------------------------------------
+template <int NC>
+struct SpSsItem {
+    static constexpr int LIST = L_SPLIT;
+    int64_t m;
+    double z[NC], lk[NC], prev[NC];
+    Eos<NC> e;
+    double theta, sgb, sext;
+    bool dem;
+    int ss, steps;
+    uint32_t fl, status;
+
+    __device__ __forceinline__ bool begin(const Ctx<NC> &c, uint32_t id)
+    {
+        m = id;
+        const MixRec<NC> &r = c.rec[m];
+        load_z<NC>(z, c.a, m);
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            e.s[i] = r.s[i];
+            e.b[i] = r.b[i];
+            lk[i] = r.lk[i];
+        }
+        theta = r.theta;
+        fl = r.fl;
+        status = r.status;
+        ss = 0;
+        steps = 0;
+        dem = false;
+        return true;
+    }
+
+    __device__ __forceinline__ void fail(const Ctx<NC> &c, uint32_t bits)
+    {
+        MixRec<NC> &r = c.rec[m];
+        int16_t it[8];
+        load_it<NC>(it, r);
+        it[5] = (int16_t)ss;
+        write_outputs_single<NC>(c, m, z, status | bits, fl, it);
+    }
+
+    __device__ __forceinline__ bool step(const Ctx<NC> &c)
+    {
+        const FlashArgs &a = c.a;
+        double x[NC], y[NC];
+        if (!xy_from_lnk<NC>(x, y, lk, z, theta, fl)) {
+            fail(c, kStRrNoRoot | kStSplitFailed);
+            return true;
+        }
+        Phase<NC> o;
+        phase_eval<NC>(o, e, c.pr.K, x, fl);
+        double r0[NC];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) r0[i] = o.lnphi[i];
+        phase_eval<NC>(o, e, c.pr.K, y, fl);
+        // G per unit feed (eq. gibbs) where an acceleration check needs it
+        const bool dem_next = a.dem_every > 0 && ss + 1 >= 2 && ((ss + 1) % a.dem_every) == 0;
+        double G = 0.0;
+        if (dem || dem_next) {
+#pragma unroll
+            for (int i = 0; i < NC; ++i)
+                G += (1.0 - theta) * x[i] * (log(x[i]) + r0[i]) + theta * y[i] * (log(y[i]) + o.lnphi[i]);
+            fl += 10 * NC;
+        }
+        if (dem) {
+            // an extrapolated point is kept only if it lowers G
+            dem = false;
+            if (!(G < sgb)) {
+#pragma unroll
+                for (int i = 0; i < NC; ++i) lk[i] -= sext * prev[i];
+                if (++steps < kStepGuard) return false;
+            }
+        }
+        double s[NC], dmax = 0.0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            s[i] = (r0[i] - o.lnphi[i]) - lk[i];
+            dmax = fmax(dmax, fabs(exp(s[i]) - 1.0));
+        }
+        fl += 4 * NC;
+        const double ext = ss_update<NC>(lk, prev, s, ss + 1, a.dem_every, fl);
+        ++ss;
+        const bool conv = dmax < a.tol_split_ss;
+        if (!conv && ss < a.max_ss && ++steps < kStepGuard) {
+            if (ext > 0.0) {
+                dem = true;
+                sgb = G;
+                sext = ext;
+            }
+            return false;
+        }
+        // hand over to the trust region: n^V = theta y from the final K
+        MixRec<NC> &r = c.rec[m];
+        if (!xy_from_lnk<NC>(x, y, lk, z, theta, fl) || !(theta > 0.0 && theta < 1.0)) {
+            fail(c, kStSplitFailed | (conv ? 0u : kStSplitTr));
+            return true;
+        }
+#pragma unroll
+        for (int i = 0; i < NC; ++i) r.lk[i] = theta * y[i];
+        r.it[5] = (int16_t)ss;
+        r.fl = fl;
+        r.status = status | (conv ? 0u : kStSplitTr);
+        push(c.L, L_NT, (uint32_t)m);
+        return true;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// SpNt: trust region on G over n^V (Appendix B.2, eqs. newton_splitter,
+// split_grad, split_hess), Newton refinement, outputs
+// ---------------------------------------------------------------------------
+template <int NC>
+struct SpNtItem {
+    static constexpr int LIST = L_NT;
+    static constexpr int NP = Tri<NC>::N;
+    int64_t m;
+    double z[NC], v0[NC], v1[NC];
+    Eos<NC> e;
+    double srad, sfacc, spred, sgacc, sdprev;
+    bool spend, spol;
+    int tr, pol, steps;
+    uint32_t fl, status;
+
+    __device__ __forceinline__ bool begin(const Ctx<NC> &c, uint32_t id)
+    {
+        m = id;
+        const MixRec<NC> &r = c.rec[m];
+        load_z<NC>(z, c.a, m);
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            e.s[i] = r.s[i];
+            e.b[i] = r.b[i];
+            v0[i] = r.lk[i];
+        }
+        fl = r.fl;
+        status = r.status;
+        srad = 0.0;
+        spend = spol = false;
+        tr = pol = steps = 0;
+        return true;
+    }
+
+    // x, y from v0 = n^V: y = n^V/sum n^V, x = (z - n^V)/sum(z - n^V)
+    __device__ __forceinline__ void xy_from_nv(double (&x)[NC], double (&y)[NC], double &bv)
+    {
+        double sv = 0.0, sl = 0.0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            x[i] = z[i] - v0[i];
+            y[i] = v0[i];
+            sv += y[i];
+            sl += x[i];
+        }
+        const double iv = 1.0 / sv, il = 1.0 / sl;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) { x[i] *= il; y[i] *= iv; }
+        bv = sv;
+        fl += 5 * NC + 2;
+    }
+
+    __device__ __forceinline__ void finish(const Ctx<NC> &c, double zx, double zy,
+                                           const double (&Lf)[NP], bool savef,
+                                           const double (&vs)[NC])
+    {
+        const FlashArgs &a = c.a;
+        MixRec<NC> &r = c.rec[m];
+        int16_t it[8];
+        load_it<NC>(it, r);
+        it[6] = (int16_t)tr;
+        it[7] = (int16_t)pol;
+        double x[NC], y[NC], bv;
+        xy_from_nv(x, y, bv);
+        double lk = 0.0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) lk = fmax(lk, fabs(log(y[i] / x[i])));
+        if (!(bv > kMinPhase && bv < 1.0 - kMinPhase)) {
+            write_outputs_single<NC>(c, m, z, status | kStSplitFailed, fl, it);
+            return;
+        }
+        if (lk < 1e-6) {
+            write_outputs_single<NC>(c, m, z, status | kStSplitTrivial, fl, it);
+            return;
+        }
+        const bool swap = zx > zy;
+        if (swap) status |= kStSwapped;
+        a.label[m] = 1;
+        a.beta[m] = swap ? 1.0 - bv : bv;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            a.x[m * NC + i] = swap ? y[i] : x[i];
+            a.y[m * NC + i] = swap ? x[i] : y[i];
+        }
+        if (a.keep_factor && a.factor) {
+            // factor of H~ = D^(1/2) H' D^(1/2): row i of L' scaled by 1/v_i
+#pragma unroll
+            for (int i = 0; i < NC; ++i)
+#pragma unroll
+                for (int j = 0; j <= i; ++j)
+                    a.factor[m * NP + tri(i, j)] = savef ? Lf[tri(i, j)] / vs[i] : NAN;
+        }
+        if (a.iters) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) a.iters[m * 8 + k] = it[k];
+        }
+        if (a.status) a.status[m] = (uint16_t)status;
+        if (a.flops) a.flops[m] = fl;
+    }
+
+    __device__ __forceinline__ bool step(const Ctx<NC> &c)
+    {
+        const FlashArgs &a = c.a;
+        double w0[NC], w1[NC], bvap;
+        xy_from_nv(w0, w1, bvap);
+        // scaled Hessian H' = (I - v v' + V((1-th) Phi^V + th Phi^L)V)/(th(1-th)),
+        // v_i = sqrt(x_i y_i / z_i), accumulated over the two evaluations
+        double vs[NC];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) vs[i] = sqrt(w0[i] * w1[i] / z[i]);
+        fl += 4 * NC;
+        double F[NP], Hs[NP], dinv[NC];
+        Phase<NC> o;
+        phase_eval<NC>(o, e, c.pr.K, w0, fl);
+        phase_derivs<NC>(F, o, e, c.pr.K, fl);
+#pragma unroll
+        for (int i = 0; i < NC; ++i)
+#pragma unroll
+            for (int j = 0; j <= i; ++j) Hs[tri(i, j)] = bvap * vs[i] * vs[j] * F[tri(i, j)];
+        fl += 3 * NP;
+        double r0[NC];
+        const double Z0 = o.Z;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) r0[i] = o.lnphi[i];
+        phase_eval<NC>(o, e, c.pr.K, w1, fl);
+        phase_derivs<NC>(F, o, e, c.pr.K, fl);
+        const double th = bvap;
+        // gradient of G over n^V (eq. split_grad) and G itself (eq. gibbs)
+        double gt[NC], gs[NC], G = 0.0, gmax = 0.0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            const double fx = log(w0[i]) + r0[i];
+            const double fy = log(w1[i]) + o.lnphi[i];
+            gt[i] = fy - fx;
+            G += (z[i] - v0[i]) * fx + v0[i] * fy;
+            gmax = fmax(gmax, fabs(gt[i]));
+            gs[i] = vs[i] * gt[i];
+        }
+        fl += 11 * NC;
+        const double sc = 1.0 / (th * (1.0 - th));
+#pragma unroll
+        for (int i = 0; i < NC; ++i)
+#pragma unroll
+            for (int j = 0; j <= i; ++j) {
+                double h = Hs[tri(i, j)] + (1.0 - th) * vs[i] * vs[j] * F[tri(i, j)] - vs[i] * vs[j];
+                if (i == j) h += 1.0;
+                Hs[tri(i, j)] = h * sc;
+            }
+        fl += 8 * NP;
+        if (spend) {
+            spend = false;
+            bool accept;
+            double ratio = 1.0;
+            if (fabs(spred) < 1e-13) {
+                accept = gmax < sgacc;
+            } else {
+                ratio = (G - sfacc) / spred;
+                accept = (G < sfacc) && ratio > 0.0;
+            }
+            if (!accept) {
+                srad *= 0.5;
+#pragma unroll
+                for (int i = 0; i < NC; ++i) v0[i] = v1[i];
+                if (++steps < kStepGuard) return false;   // re-evaluate there
+                status |= kStSplitUnconv | kStStepCap;
+                finish(c, Z0, o.Z, F, false, vs);
+                return true;
+            }
+            if (ratio <= 0.25) srad *= 0.5;
+            else if (ratio >= 0.75) srad *= 2.0;
+        }
+        if (!spol && gmax < a.tol_split_tr) {
+            spol = true;   // the paper's criterion holds: refine
+            sdprev = 1e300;
+        }
+        double u[NC];
+        bool eta0;
+        if (spol) {
+            // Newton refinement while H is positive definite; an indefinite H
+            // sends the split back to the trust region
+            double rad = 1e300;
+            trust_step<NC>(u, rad, eta0, F, dinv, Hs, gs, fl);
+            if (!eta0) spol = false;
+        }
+        if (spol) {
+            double dmax = 0.0, amax = 1.0;
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                u[i] *= vs[i];
+                dmax = fmax(dmax, fabs(u[i]));
+                if (u[i] < 0.0) amax = fmin(amax, 0.99 * v0[i] / -u[i]);
+                if (u[i] > 0.0) amax = fmin(amax, 0.99 * (z[i] - v0[i]) / u[i]);
+            }
+#pragma unroll
+            for (int i = 0; i < NC; ++i) v0[i] += amax * u[i];
+            fl += 6 * NC;
+            // converged: step below tol_polish, or rounding-size steps that no
+            // longer shrink
+            const bool conv = dmax < a.tol_polish || (dmax < 1e-10 && dmax >= 0.5 * sdprev);
+            if (conv || pol >= a.max_polish || ++steps >= kStepGuard) {
+                if (!conv && !(dmax < 1e-10)) status |= kStSplitUnconv;
+                finish(c, Z0, o.Z, F, true, vs);
+                return true;
+            }
+            sdprev = dmax;
+            ++pol;
+            return false;
+        }
+        if (tr >= a.max_tr_split || ++steps >= kStepGuard) {
+            status |= kStSplitUnconv;
+            finish(c, Z0, o.Z, F, false, vs);
+            return true;
+        }
+        status |= kStSplitTr;
+        double pr = trust_step<NC>(u, srad, eta0, F, dinv, Hs, gs, fl);
+        // dn = v o u, kept inside 0 < n^V < z
+        double amax = 1.0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            u[i] *= vs[i];
+            if (u[i] < 0.0) amax = fmin(amax, 0.99 * v0[i] / -u[i]);
+            if (u[i] > 0.0) amax = fmin(amax, 0.99 * (z[i] - v0[i]) / u[i]);
+        }
+        if (amax < 1.0) {
+            double gu = 0.0;
+#pragma unroll
+            for (int i = 0; i < NC; ++i) gu += gt[i] * u[i];
+            pr = amax * gu + amax * amax * (pr - gu);
+        }
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            v1[i] = v0[i];
+            v0[i] += amax * u[i];
+        }
+        fl += 6 * NC;
+        sfacc = G;
+        sgacc = gmax;
+        spred = pr;
+        spend = true;
+        ++tr;
+        return false;
+    }
+};
+
+}  // namespace ptf

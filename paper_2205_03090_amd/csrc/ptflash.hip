@@ -1,18 +1,22 @@
 // ptflash.hip -- kernels and C ABI of the gfx950 SRK PT flash.
 //
-// Persistent form: a grid sized to the device; every wavefront keeps one
-// mixture per lane and, whenever lanes finish, takes the next mixture
-// indices from a device counter (one atomic per wavefront and step), so
-// converged mixtures leave the wave immediately and their lanes are reused.
-// This is the paper's "synchronizer" (save converged rows, drop them from
-// the active set; Sec. 3, Algorithm 1) done per lane inside one launch.
+// The flash runs as a pipeline of stage kernels (flash_stages.hpp): every
+// stage is a persistent grid whose wavefronts take work items (mixtures or
+// stability trials) from a device list, one item per lane, and refill a lane
+// as soon as its item finishes; an item that needs a later stage is appended
+// to that stage's list.  This is the paper's synchronizer (save converged
+// rows, drop them from the active set) and its barrier per stage (Sec. 3,
+// Algorithm 1), done on the device without host synchronisation: the kernel
+// order on the stream is the barrier.  The plain form runs the same items
+// one step per launch, with compaction and a host read of the active count
+// after every launch.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstring>
 
 #include "ptflash.h"
-#include "flash_lane.hpp"
+#include "flash_stages.hpp"
 #include "adjoint_device.hpp"
 
 namespace ptf {
@@ -21,37 +25,97 @@ constexpr int kMinNc = 2;
 constexpr int kMaxNc = PTF_MAX_NC;
 constexpr int kBlock = 256;
 
-__global__ void reset_counter(unsigned long long *q) { *q = 0ull; }
-
-template <int NC>
-__global__ void __launch_bounds__(kBlock)
-flash_persistent(FlashArgs a, const double *__restrict__ Tc, const double *__restrict__ Pc,
-                 const double *__restrict__ om, const double *__restrict__ K,
-                 unsigned long long *__restrict__ queue)
+__global__ void reset_counters(unsigned long long *q, int n)
 {
-    const Props pr{Tc, Pc, om, K};
-    Lane<NC> L;
-    L.stage = ST_IDLE;
+    if ((int)threadIdx.x < n) q[threadIdx.x] = 0ull;
+}
+
+// Number of items of a stage: all mixtures for the first stage, else the
+// length of the stage's list (written by the previous stages).
+template <class Item, int NC>
+__device__ __forceinline__ int64_t stage_count(const Ctx<NC> &c)
+{
+    return Item::LIST < 0 ? c.a.n : (int64_t)c.L.count[Item::LIST];
+}
+
+template <class Item, int NC>
+__device__ __forceinline__ uint32_t stage_id(const Ctx<NC> &c, int64_t k)
+{
+    return Item::LIST < 0 ? (uint32_t)k : c.L.ids[Item::LIST < 0 ? 0 : Item::LIST][k];
+}
+
+// Persistent stage: one item per lane; lanes whose item finished take the
+// next indices from *take (one atomic per wavefront and step).  Every item
+// finishes within its stage's iteration caps (and kStepGuard steps), so every
+// wavefront reaches the exit.
+template <class Item, int NC>
+__global__ void __launch_bounds__(kBlock)
+stage_persistent(Ctx<NC> c, const double *__restrict__ Tc, const double *__restrict__ Pc,
+                 const double *__restrict__ om, const double *__restrict__ K,
+                 unsigned long long *__restrict__ take)
+{
+    c.pr = Props{Tc, Pc, om, K};
+    const int64_t count = stage_count<Item, NC>(c);
+    Item it;
+    bool live = false, gone = false;
     const int lane = (int)__lane_id();
     for (;;) {
-        const bool want = (L.stage == ST_IDLE);
+        const bool want = !live && !gone;
         const unsigned long long mask = __ballot(want);
         if (mask) {
             const int leader = __ffsll((unsigned long long)mask) - 1;
             unsigned long long base = 0;
-            if (lane == leader) base = atomicAdd(queue, (unsigned long long)__popcll(mask));
+            if (lane == leader) base = atomicAdd(take, (unsigned long long)__popcll(mask));
             const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)base, leader);
             const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(base >> 32), leader);
             base = ((unsigned long long)hi << 32) | lo;
             if (want) {
                 const unsigned long long below = mask & ((1ull << lane) - 1ull);
-                const long long mi = (long long)(base + (unsigned long long)__popcll(below));
-                if (mi < a.n) L.start(mi, a, pr);
-                else L.stage = ST_GONE;
+                const int64_t k = (int64_t)(base + (unsigned long long)__popcll(below));
+                if (k < count) live = it.begin(c, stage_id<Item, NC>(c, k));
+                else gone = true;
             }
         }
-        if (__ballot(L.stage != ST_GONE) == 0ull) break;
-        L.step(a, pr);
+        if (__ballot(!gone) == 0ull) break;
+        if (live) live = !it.step(c);
+    }
+}
+
+// Plain form: begin every item of the stage and list the live ones ...
+template <class Item, int NC>
+__global__ void __launch_bounds__(kBlock)
+stage_plain_begin(Ctx<NC> c, const double *__restrict__ Tc, const double *__restrict__ Pc,
+                  const double *__restrict__ om, const double *__restrict__ K, Item *states,
+                  uint32_t *active, unsigned long long *nactive)
+{
+    c.pr = Props{Tc, Pc, om, K};
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= stage_count<Item, NC>(c)) return;
+    Item it;
+    if (it.begin(c, stage_id<Item, NC>(c, k))) {
+        states[k] = it;
+        active[atomicAdd(nactive, 1ull)] = (uint32_t)k;
+    }
+}
+
+// ... then one step of every live item per launch, listing those still live
+// (the list order does not matter: each item's result depends on its own
+// state only).
+template <class Item, int NC>
+__global__ void __launch_bounds__(kBlock)
+stage_plain_step(Ctx<NC> c, const double *__restrict__ Tc, const double *__restrict__ Pc,
+                 const double *__restrict__ om, const double *__restrict__ K, Item *states,
+                 const uint32_t *__restrict__ active, int64_t nact, uint32_t *next,
+                 unsigned long long *nnext)
+{
+    c.pr = Props{Tc, Pc, om, K};
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nact) return;
+    const uint32_t k = active[j];
+    Item it = states[k];
+    if (!it.step(c)) {
+        states[k] = it;
+        next[atomicAdd(nnext, 1ull)] = k;
     }
 }
 
@@ -86,66 +150,6 @@ eval_phase_kernel(int64_t n, const double *__restrict__ c, const double *__restr
                 phi[m * NC * NC + i * NC + j] = F[tri(i, j)];
                 phi[m * NC * NC + j * NC + i] = F[tri(i, j)];
             }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Plain form: the paper's synchronizer with a barrier per stage (Sec. 3,
-// Algorithm 1).  Per-mixture state lives in global memory; each launch
-// advances every mixture of the current stage by one step; a compaction
-// kernel then lists the mixtures still in that stage and the host reads the
-// count.  Stages run in order, so a stage starts only when the previous one
-// has no mixture left.  The per-mixture arithmetic is Lane::step(), the same
-// as in the persistent form.
-// ---------------------------------------------------------------------------
-
-template <int NC>
-__global__ void __launch_bounds__(kBlock)
-plain_init(FlashArgs a, const double *__restrict__ Tc, const double *__restrict__ Pc,
-           const double *__restrict__ om, const double *__restrict__ K, Lane<NC> *states,
-           int32_t *list, unsigned long long *count)
-{
-    const Props pr{Tc, Pc, om, K};
-    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= a.n) return;
-    Lane<NC> L;
-    L.start(m, a, pr);
-    states[m] = L;
-    if (L.stage == ST_FEED) {
-        const unsigned long long k = atomicAdd(count, 1ull);
-        list[k] = (int32_t)m;
-    }
-}
-
-template <int NC>
-__global__ void __launch_bounds__(kBlock)
-plain_step(FlashArgs a, const double *__restrict__ Tc, const double *__restrict__ Pc,
-           const double *__restrict__ om, const double *__restrict__ K, Lane<NC> *states,
-           const int32_t *__restrict__ list, int64_t count)
-{
-    const Props pr{Tc, Pc, om, K};
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= count) return;
-    const int32_t m = list[k];
-    Lane<NC> L = states[m];
-    L.step(a, pr);
-    states[m] = L;
-}
-
-// Lists the mixtures of `in` whose stage equals (keep_equal = 1) or differs
-// from (keep_equal = 0) `stage`; the order is not deterministic, which does
-// not matter since each mixture's result depends on its own state only.
-template <int NC>
-__global__ void __launch_bounds__(kBlock)
-plain_compact(const Lane<NC> *__restrict__ states, const int32_t *__restrict__ in,
-              int64_t count, int stage, int keep_equal, int32_t *out, unsigned long long *outc)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= count) return;
-    const int32_t m = in[k];
-    if ((states[m].stage == stage) == (keep_equal != 0)) {
-        const unsigned long long j = atomicAdd(outc, 1ull);
-        out[j] = m;
     }
 }
 
@@ -335,11 +339,6 @@ static void fill_args(FlashArgs &a, const ptflash_problem *p, const ptflash_opti
     a.max_tr_split = o->max_tr_split;
     a.max_polish = o->max_polish;
     a.dem_every = o->dem_every;
-    // every stage's evaluations are bounded by its caps (a rejected
-    // trust-region step costs one extra evaluation); the cap below is a
-    // safety net that guarantees termination
-    a.max_steps = 8 + o->max_pre_ss + (o->max_ss + 2 + 2 * o->max_tr_sa) +
-                  (o->max_ss + 2) + (2 * o->max_tr_split + o->max_polish + 4);
     a.keep_factor = o->keep_factor;
     a.tol_sa_ss = o->tol_sa_ss;
     a.tol_sa_tr = o->tol_sa_tr;
@@ -357,39 +356,110 @@ static void fill_args(FlashArgs &a, const ptflash_problem *p, const ptflash_opti
     a.factor = r->factor;
 }
 
+static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace: counters | per-mixture records | stage lists | (plain form:)
+// item states and two active lists.
+constexpr int kNumCounters = 16;   // L_COUNT list counts, 6 take counters, 2 plain
+constexpr int kTake0 = L_COUNT;
+constexpr int kPlain0 = L_COUNT + 6;
+
 template <int NC>
-static int launch_persistent(const FlashArgs &a, const ptflash_problem *p,
-                             const ptflash_options *o, unsigned long long *queue,
-                             hipStream_t s)
+static size_t plain_state_bytes()
+{
+    size_t m = sizeof(PreItem<NC>);
+    m = m > sizeof(SaSsItem<NC>) ? m : sizeof(SaSsItem<NC>);
+    m = m > sizeof(SaTrItem<NC>) ? m : sizeof(SaTrItem<NC>);
+    m = m > sizeof(SaFinItem<NC>) ? m : sizeof(SaFinItem<NC>);
+    m = m > sizeof(SpSsItem<NC>) ? m : sizeof(SpSsItem<NC>);
+    m = m > sizeof(SpNtItem<NC>) ? m : sizeof(SpNtItem<NC>);
+    return m;
+}
+
+template <int NC>
+static size_t workspace_bytes(int64_t n, int form)
+{
+    const size_t un = (size_t)n;
+    size_t b = 256 + align256(un * sizeof(MixRec<NC>)) + 3 * align256(2 * un * 4) +
+               3 * align256(un * 4);
+    if (form == PTFLASH_FORM_PLAIN)
+        b += align256(2 * un * plain_state_bytes<NC>()) + 2 * align256(2 * un * 4);
+    return b;
+}
+
+struct Carve {
+    char *p;
+    template <typename T>
+    T *take(size_t bytes)
+    {
+        T *r = (T *)p;
+        p += align256(bytes);
+        return r;
+    }
+};
+
+template <int NC>
+static void setup_ctx(Ctx<NC> &c, const FlashArgs &a, int64_t n, void *ws, char **tail)
+{
+    Carve cv{(char *)ws};
+    c.a = a;
+    c.pr = Props{nullptr, nullptr, nullptr, nullptr};
+    unsigned long long *cnt = cv.take<unsigned long long>(256);
+    c.rec = cv.take<MixRec<NC>>((size_t)n * sizeof(MixRec<NC>));
+    c.L.ids[L_SA] = cv.take<uint32_t>(2 * (size_t)n * 4);
+    c.L.ids[L_SATR] = cv.take<uint32_t>(2 * (size_t)n * 4);
+    cv.take<uint32_t>(2 * (size_t)n * 4);   // spare (keeps the layout aligned to the size formula)
+    c.L.ids[L_SAFIN] = cv.take<uint32_t>((size_t)n * 4);
+    c.L.ids[L_SPLIT] = cv.take<uint32_t>((size_t)n * 4);
+    c.L.ids[L_NT] = cv.take<uint32_t>((size_t)n * 4);
+    c.L.count = cnt;
+    *tail = cv.p;
+}
+
+static int grid_for(const void *kernel, int block, int requested)
+{
+    if (requested > 0) return requested;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess)
+        return -1;
+    const int cus = device_cus();
+    if (cus <= 0) return -1;
+    return (per_cu > 0 ? per_cu : 1) * cus;
+}
+
+template <class Item, int NC>
+static int run_persistent_stage(const Ctx<NC> &c, const ptflash_problem *p,
+                                const ptflash_options *o, int take_slot, hipStream_t s)
 {
     const int block = o->block > 0 ? o->block : kBlock;
     if (block % 64 != 0 || block > kBlock) return PTFLASH_EINVAL;
-    int grid = o->grid;
-    if (grid <= 0) {
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, flash_persistent<NC>, block,
-                                                         0) != hipSuccess)
-            return PTFLASH_EHIP;
-        const int cus = device_cus();
-        if (cus <= 0) return PTFLASH_EHIP;
-        grid = (per_cu > 0 ? per_cu : 1) * cus;
-    }
-    hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, s, queue);
-    hipLaunchKernelGGL(flash_persistent<NC>, dim3(grid), dim3(block), 0, s, a, p->Tc, p->Pc,
-                       p->omega, p->kij, queue);
+    const int grid = grid_for((const void *)stage_persistent<Item, NC>, block, o->grid);
+    if (grid <= 0) return PTFLASH_EHIP;
+    hipLaunchKernelGGL((stage_persistent<Item, NC>), dim3(grid), dim3(block), 0, s, c, p->Tc,
+                       p->Pc, p->omega, p->kij, c.L.count + take_slot);
     return hipGetLastError() == hipSuccess ? PTFLASH_OK : PTFLASH_EHIP;
 }
 
-static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
 template <int NC>
-static size_t plain_workspace(int64_t n)
+static int launch_persistent(const FlashArgs &a, const ptflash_problem *p,
+                             const ptflash_options *o, void *ws, hipStream_t s)
 {
-    return 256 + align256((size_t)n * sizeof(Lane<NC>)) + 3 * align256((size_t)n * sizeof(int32_t));
+    Ctx<NC> c;
+    char *tail;
+    setup_ctx<NC>(c, a, p->n, ws, &tail);
+    hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, c.L.count, kNumCounters);
+    int rc;
+    if ((rc = run_persistent_stage<PreItem<NC>, NC>(c, p, o, kTake0 + 0, s))) return rc;
+    if ((rc = run_persistent_stage<SaSsItem<NC>, NC>(c, p, o, kTake0 + 1, s))) return rc;
+    if ((rc = run_persistent_stage<SaTrItem<NC>, NC>(c, p, o, kTake0 + 2, s))) return rc;
+    if ((rc = run_persistent_stage<SaFinItem<NC>, NC>(c, p, o, kTake0 + 3, s))) return rc;
+    if ((rc = run_persistent_stage<SpSsItem<NC>, NC>(c, p, o, kTake0 + 4, s))) return rc;
+    if ((rc = run_persistent_stage<SpNtItem<NC>, NC>(c, p, o, kTake0 + 5, s))) return rc;
+    return PTFLASH_OK;
 }
 
-// Reads the device counter after the work queued so far (host sync).
-static int read_count(unsigned long long *dcnt, int64_t &out, hipStream_t s)
+// Reads a device counter after the work queued so far (host sync).
+static int read_count(const unsigned long long *dcnt, int64_t &out, hipStream_t s)
 {
     unsigned long long h = 0;
     if (hipGetLastError() != hipSuccess) return PTFLASH_EHIP;
@@ -400,54 +470,51 @@ static int read_count(unsigned long long *dcnt, int64_t &out, hipStream_t s)
     return PTFLASH_OK;
 }
 
+template <class Item, int NC>
+static int run_plain_stage(const Ctx<NC> &c, const ptflash_problem *p, char *tail, hipStream_t s)
+{
+    const int64_t n = p->n;
+    Carve cv{tail};
+    Item *states = cv.take<Item>(2 * (size_t)n * plain_state_bytes<NC>());
+    uint32_t *la = cv.take<uint32_t>(2 * (size_t)n * 4);
+    uint32_t *lb = cv.take<uint32_t>(2 * (size_t)n * 4);
+    unsigned long long *na = c.L.count + kPlain0, *nb = c.L.count + kPlain0 + 1;
+    int64_t count = n;
+    int rc;
+    if (Item::LIST >= 0 && (rc = read_count(c.L.count + Item::LIST, count, s))) return rc;
+    if (count == 0) return PTFLASH_OK;
+    auto grid = [](int64_t k) { return dim3((unsigned)((k + kBlock - 1) / kBlock)); };
+    hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, na, 1);
+    hipLaunchKernelGGL((stage_plain_begin<Item, NC>), grid(count), dim3(kBlock), 0, s, c, p->Tc,
+                       p->Pc, p->omega, p->kij, states, la, na);
+    int64_t nact = 0;
+    if ((rc = read_count(na, nact, s))) return rc;
+    for (int guard = 0; nact > 0 && guard <= kStepGuard + 1; ++guard) {
+        hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, nb, 1);
+        hipLaunchKernelGGL((stage_plain_step<Item, NC>), grid(nact), dim3(kBlock), 0, s, c, p->Tc,
+                           p->Pc, p->omega, p->kij, states, la, nact, lb, nb);
+        if ((rc = read_count(nb, nact, s))) return rc;
+        uint32_t *t = la; la = lb; lb = t;
+        unsigned long long *tc = na; na = nb; nb = tc;
+    }
+    return PTFLASH_OK;
+}
+
 template <int NC>
 static int launch_plain(const FlashArgs &a, const ptflash_problem *p, void *ws, hipStream_t s)
 {
-    char *base = (char *)ws;
-    unsigned long long *cnt = (unsigned long long *)base;
-    const size_t st = align256((size_t)p->n * sizeof(Lane<NC>));
-    const size_t li = align256((size_t)p->n * sizeof(int32_t));
-    Lane<NC> *states = (Lane<NC> *)(base + 256);
-    int32_t *live = (int32_t *)(base + 256 + st);
-    int32_t *wa = (int32_t *)(base + 256 + st + li);
-    int32_t *wb = (int32_t *)(base + 256 + st + 2 * li);
-    auto grid = [](int64_t c) { return dim3((unsigned)((c + kBlock - 1) / kBlock)); };
-    hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, s, cnt);
-    hipLaunchKernelGGL(plain_init<NC>, grid(p->n), dim3(kBlock), 0, s, a, p->Tc, p->Pc,
-                       p->omega, p->kij, states, live, cnt);
-    int64_t nlive = 0;
-    int rc = read_count(cnt, nlive, s);
-    if (rc) return rc;
-    const int stages[5] = {ST_FEED, ST_PRE, ST_SA, ST_SPLIT_SS, ST_SPLIT_NT};
-    for (int si = 0; si < 5 && nlive > 0; ++si) {
-        const int stage = stages[si];
-        // barrier: the stage starts with every live mixture that reached it
-        int64_t nw = 0;
-        hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, s, cnt);
-        hipLaunchKernelGGL(plain_compact<NC>, grid(nlive), dim3(kBlock), 0, s, states, live,
-                           nlive, stage, 1, wa, cnt);
-        if ((rc = read_count(cnt, nw, s))) return rc;
-        int32_t *work = wa, *spare = wb;
-        for (int guard = 0; nw > 0 && guard <= a.max_steps; ++guard) {
-            hipLaunchKernelGGL(plain_step<NC>, grid(nw), dim3(kBlock), 0, s, a, p->Tc, p->Pc,
-                               p->omega, p->kij, states, work, nw);
-            hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, s, cnt);
-            hipLaunchKernelGGL(plain_compact<NC>, grid(nw), dim3(kBlock), 0, s, states, work, nw,
-                               stage, 1, spare, cnt);
-            if ((rc = read_count(cnt, nw, s))) return rc;
-            int32_t *t = work; work = spare; spare = t;
-        }
-        // drop finished mixtures from the live list
-        hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, s, cnt);
-        hipLaunchKernelGGL(plain_compact<NC>, grid(nlive), dim3(kBlock), 0, s, states, live,
-                           nlive, (int)ST_IDLE, 0, wb, cnt);
-        if ((rc = read_count(cnt, nlive, s))) return rc;
-        if (nlive > 0 &&
-            hipMemcpyAsync(live, wb, (size_t)nlive * sizeof(int32_t), hipMemcpyDeviceToDevice, s) !=
-                hipSuccess)
-            return PTFLASH_EHIP;
-    }
-    return hipGetLastError() == hipSuccess ? PTFLASH_OK : PTFLASH_EHIP;
+    Ctx<NC> c;
+    char *tail;
+    setup_ctx<NC>(c, a, p->n, ws, &tail);
+    hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, c.L.count, kNumCounters);
+    int rc;
+    if ((rc = run_plain_stage<PreItem<NC>, NC>(c, p, tail, s))) return rc;
+    if ((rc = run_plain_stage<SaSsItem<NC>, NC>(c, p, tail, s))) return rc;
+    if ((rc = run_plain_stage<SaTrItem<NC>, NC>(c, p, tail, s))) return rc;
+    if ((rc = run_plain_stage<SaFinItem<NC>, NC>(c, p, tail, s))) return rc;
+    if ((rc = run_plain_stage<SpSsItem<NC>, NC>(c, p, tail, s))) return rc;
+    if ((rc = run_plain_stage<SpNtItem<NC>, NC>(c, p, tail, s))) return rc;
+    return PTFLASH_OK;
 }
 
 template <int NC>
@@ -477,9 +544,9 @@ struct Dispatch {
 template <int NC>
 struct PersistentF {
     static int run(const FlashArgs &a, const ptflash_problem *p, const ptflash_options *o,
-                   unsigned long long *q, hipStream_t s)
+                   void *ws, hipStream_t s)
     {
-        return launch_persistent<NC>(a, p, o, q, s);
+        return launch_persistent<NC>(a, p, o, ws, s);
     }
 };
 
@@ -492,10 +559,10 @@ struct PlainF {
 };
 
 template <int NC>
-struct PlainWsF {
-    static int run(int64_t n, size_t *out)
+struct WsF {
+    static int run(int64_t n, int form, size_t *out)
     {
-        *out = plain_workspace<NC>(n);
+        *out = workspace_bytes<NC>(n, form);
         return PTFLASH_OK;
     }
 };
@@ -570,12 +637,9 @@ int32_t ptflash_max_nc(void) { return kMaxNc; }
 size_t ptflash_workspace_bytes(const ptflash_problem *p, const ptflash_options *o)
 {
     if (!problem_ok(p) || !o) return 0;
-    if (o->form == PTFLASH_FORM_PLAIN) {
-        size_t b = 0;
-        if (Dispatch<PlainWsF>::run(p->nc, p->n, &b) != PTFLASH_OK) return 0;
-        return b;
-    }
-    return 256;
+    size_t b = 0;
+    if (Dispatch<WsF>::run(p->nc, p->n, o->form, &b) != PTFLASH_OK) return 0;
+    return b;
 }
 
 int ptflash_flash(const ptflash_problem *p, const ptflash_options *o, ptflash_result *r,
@@ -585,7 +649,7 @@ int ptflash_flash(const ptflash_problem *p, const ptflash_options *o, ptflash_re
     if (p->nc < kMinNc || p->nc > kMaxNc) return PTFLASH_EUNSUPPORTED;
     if (p->props_per_mixture != 0) return PTFLASH_EUNSUPPORTED;
     if (p->n == 0) return PTFLASH_OK;
-    if (o->form == PTFLASH_FORM_PLAIN && p->n > INT32_MAX) return PTFLASH_EUNSUPPORTED;
+    if (p->n > (int64_t)1 << 30) return PTFLASH_EUNSUPPORTED;   // trial ids are 2m + t in 32 bits
     if (!r->label || !r->beta || !r->x || !r->y) return PTFLASH_EINVAL;
     if (o->keep_factor && !r->factor) return PTFLASH_EINVAL;
     if (!ws || ws_bytes < ptflash_workspace_bytes(p, o)) return PTFLASH_EWORKSPACE;
@@ -593,7 +657,7 @@ int ptflash_flash(const ptflash_problem *p, const ptflash_options *o, ptflash_re
     FlashArgs a;
     fill_args(a, p, o, r);
     if (o->form == PTFLASH_FORM_PLAIN) return Dispatch<PlainF>::run(p->nc, a, p, ws, s);
-    return Dispatch<PersistentF>::run(p->nc, a, p, o, (unsigned long long *)ws, s);
+    return Dispatch<PersistentF>::run(p->nc, a, p, o, ws, s);
 }
 
 int ptflash_eval_phase(int64_t n, int32_t nc, const double *c, const double *T,
