@@ -320,6 +320,23 @@ static int orc_gepp(int n, double *M, double *rhs)
     return 0;
 }
 
+/* 1 when the symmetric n x n matrix M is positive definite: Gaussian
+ * elimination without pivoting (the LDL^T factorisation) has only positive
+ * pivots (Sylvester's criterion).  M is not modified. */
+static int orc_pos_def(int n, const double *M)
+{
+    double A[ORC_NCMAX * ORC_NCMAX];
+    memcpy(A, M, sizeof(double) * n * n);
+    for (int k = 0; k < n; ++k) {
+        if (!(A[k * n + k] > 0.0) || !isfinite(A[k * n + k])) return 0;
+        for (int r = k + 1; r < n; ++r) {
+            double f = A[r * n + k] / A[k * n + k];
+            for (int c = k; c < n; ++c) A[r * n + c] -= f * A[k * n + c];
+        }
+    }
+    return 1;
+}
+
 /* ---------------------------------------------------------------------- */
 /* Tangent plane distances (Sec. 2.2.1, eqs. tpd and tm)                   */
 /* ---------------------------------------------------------------------- */
@@ -442,10 +459,13 @@ enum { ORC_MIN_TOL = 0, ORC_MIN_BELOW = 1, ORC_MIN_CAP = 2, ORC_MIN_STUCK = 3 };
 
 /* Newton's method on grad f = 0 with a symmetric central-difference Hessian,
  * Levenberg-Marquardt damping (H + mu D) p = -grad in the metric D whenever
- * the Newton step is not a descent direction or the line search cuts it,
+ * H is not positive definite or the line search cuts the step,
  * a fraction-to-the-boundary rule for the box, and Armijo backtracking on f.
- * Close to the stationary point (max |grad| < 1e-5), where f changes less
- * than its rounding, a step is accepted when it lowers max |grad|. */
+ * Close to the stationary point (max |grad| < 1e-5), where f may change
+ * less than its rounding, a step that fails Armijo is still accepted when it
+ * lowers the gradient and does not raise f beyond rounding (1e-13 |f|): the
+ * method stays a descent method, like the paper's trust regions, whose steps
+ * are judged on the decrease of the objective (Appendix B). */
 static int orc_minimise(const orc_minprob *pr, double *x, int *n_it, double *f_out)
 {
     int n = pr->n;
@@ -494,7 +514,10 @@ static int orc_minimise(const orc_minprob *pr, double *x, int *n_it, double *f_o
         for (;; ++tries) {
             memcpy(M, H, sizeof(double) * n * n);
             for (int i = 0; i < n; ++i) { M[i * n + i] += mu * dm[i]; p[i] = -g[i]; }
-            int bad = orc_gepp(n, M, p);
+            /* the model must be convex (as a trust-region step's shifted
+             * Hessian is): with an indefinite H the Newton step heads for a
+             * saddle, such as the trivial point of an unstable feed */
+            int bad = !orc_pos_def(n, M) || orc_gepp(n, M, p);
             slope = 0.0;
             for (int i = 0; i < n; ++i) slope += g[i] * p[i];
             if (!bad && slope < 0.0) break;
@@ -511,16 +534,20 @@ static int orc_minimise(const orc_minprob *pr, double *x, int *n_it, double *f_o
         for (; cuts < 60; ++cuts) {
             for (int i = 0; i < n; ++i) xt[i] = x[i] + a * p[i];
             double ft = pr->fn(pr->ctx, xt, gt);
-            if (local) {
+            /* sufficient decrease of the objective (Armijo) ... */
+            acc = ft <= f + 1e-4 * a * slope;
+            if (!acc && local) {
+                /* ... or, near a stationary point where the decrease is at
+                 * the rounding level of f, a smaller gradient with f not
+                 * above rounding of its current value (a descent method:
+                 * it never climbs to a saddle such as the trivial point) */
                 double tmax = 0.0, t2 = 0.0, g2 = 0.0;
                 for (int i = 0; i < n; ++i) {
                     if (fabs(gt[i]) > tmax) tmax = fabs(gt[i]);
                     t2 += gt[i] * gt[i];
                     g2 += g[i] * g[i];
                 }
-                acc = tmax < gmax || t2 < g2;
-            } else {
-                acc = ft <= f + 1e-4 * a * slope;
+                acc = (tmax < gmax || t2 < g2) && ft <= f + 1e-13 * fmax(1.0, fabs(f));
             }
             if (acc) break;
             a *= 0.5;

@@ -4,7 +4,11 @@ tests, the smoke check and the benchmark's checks).
 Rule: labels must be identical wherever the oracle's |min TPD| > 1e-9; where
 both sides report two phases (outside the same band), beta, x and y agree
 within 1e-10 absolute; where both report one phase, beta = -1 and
-x = y = z/sum(z) bit for bit.
+x = y = z/sum(z) bit for bit.  A two-phase row whose oracle split did not
+converge (the oracle's SPLIT_UNCONV flag) has no reference values; when the
+workload is given, the GPU's split there must instead satisfy equal
+fugacities (max |ln y_i phi_i(y) - ln x_i phi_i(x)| < 1e-9, evaluated by the
+oracle's phase model) and the material balance.
 """
 from __future__ import annotations
 
@@ -12,6 +16,19 @@ import numpy as np
 
 TOL = 1e-10
 BAND = 1e-9
+FUG_TOL = 1e-9
+ORC_SPLIT_UNCONV = 4
+
+
+def split_residual_max(w, m: int, x, y) -> float:
+    """max_i |ln y_i + ln phi_i(y) - ln x_i - ln phi_i(x)| with the oracle's
+    phase model, for mixture m of workload w."""
+    import oracle
+    sets = (w.Tc[m], w.Pc[m], w.omega[m], w.kij[m]) if w.per_mixture else \
+        (w.Tc, w.Pc, w.omega, w.kij)
+    lx, _ = oracle.lnphi(*sets, w.T[m], w.P[m], x)
+    ly, _ = oracle.lnphi(*sets, w.T[m], w.P[m], y)
+    return float(np.abs(np.log(y) + ly - np.log(x) - lx).max())
 
 
 def gpu_to_numpy(r):
@@ -22,8 +39,10 @@ def gpu_to_numpy(r):
     return out
 
 
-def compare(g: dict, o: dict, idx=None, verbose: bool = True) -> dict:
-    """g: GPU arrays (full batch); o: oracle arrays for rows idx (or all)."""
+def compare(g: dict, o: dict, idx=None, verbose: bool = True, w=None) -> dict:
+    """g: GPU arrays (full batch); o: oracle arrays for rows idx (or all);
+    w: the workload of the full batch (enables the checks of rows whose
+    oracle split did not converge)."""
     if idx is None:
         idx = np.arange(len(o["label"]))
     gl, ol = g["label"][idx].astype(int), o["label"].astype(int)
@@ -32,7 +51,10 @@ def compare(g: dict, o: dict, idx=None, verbose: bool = True) -> dict:
     lab_bad = np.where(decisive & (gl != ol))[0]
     # values are compared where both report two phases outside the band
     # (within it G is flat to ~1e-9 and distinct stationary points compete)
-    both2 = np.where((gl == 1) & (ol == 1) & decisive)[0]
+    # and the oracle's split converged
+    ref_unconv = (o["info"][:, 8] & ORC_SPLIT_UNCONV) != 0
+    unc2 = np.where((gl == 1) & (ol == 1) & decisive & ref_unconv)[0]
+    both2 = np.where((gl == 1) & (ol == 1) & decisive & ~ref_unconv)[0]
     both1 = np.where((gl == 0) & (ol == 0))[0]
     db = np.abs(g["beta"][idx][both2] - o["beta"][both2]) if len(both2) else np.zeros(0)
     dx = np.abs(g["x"][idx][both2] - o["x"][both2]).max(1) if len(both2) else np.zeros(0)
@@ -42,11 +64,27 @@ def compare(g: dict, o: dict, idx=None, verbose: bool = True) -> dict:
     one_bad = both1[(g["beta"][idx][both1] != -1.0) |
                     np.any(g["x"][idx][both1] != o["x"][both1], axis=1) |
                     np.any(g["y"][idx][both1] != o["y"][both1], axis=1)]
+    # rows without a converged reference: the GPU split must be valid
+    unc_bad, unc_res = [], 0.0
+    if w is not None:
+        for k in unc2:
+            m = idx[k]
+            xr, yr, b = g["x"][m], g["y"][m], g["beta"][m]
+            zz = w.z[m] / np.cumsum(w.z[m])[-1]
+            res = split_residual_max(w, m, xr, yr)
+            mb = float(np.abs((1 - b) * xr + b * yr - zz).max())
+            unc_res = max(unc_res, res)
+            if not (res < FUG_TOL and mb < 1e-13):
+                unc_bad.append(k)
+    else:
+        unc_bad = list(unc2)
+    val_bad = np.concatenate([val_bad, np.asarray(unc_bad, dtype=val_bad.dtype)])
     rep = dict(n=len(idx), two_phase=int(len(both2)), single=int(len(both1)),
                label_mismatch=int(len(lab_bad)), value_mismatch=int(len(val_bad)),
                single_mismatch=int(len(one_bad)),
                max_err=float(err.max()) if len(err) else 0.0,
-               band_excluded=int((~decisive).sum()))
+               band_excluded=int((~decisive).sum()),
+               ref_unconverged=int(len(unc2)), ref_unconverged_residual=unc_res)
     # path agreement of the substitution counters (same algorithm on both sides)
     oi, gi = o["info"], g["iters"][idx]
     same = (gi[:, 0] == oi[:, 1]) & (gi[:, 1] == oi[:, 2]) & (gi[:, 3] == oi[:, 4]) & \

@@ -193,3 +193,18 @@ def test_case3_shortcut_is_a_proof_of_instability(orc, nc8):
     r2 = orc.flash(sub, want_min_tpd=1, threads=8)
     assert np.all(r2["min_tpd"] < -1e-10)
     assert np.array_equal(r2["label"], r["label"][idx])
+
+
+def test_parity_validity_check_for_unconverged_references(orc, nc8):
+    # the check applied where the oracle's split did not converge: it passes
+    # the oracle's own converged splits and fails a perturbed one
+    from parity import FUG_TOL, split_residual_max
+    w, r = nc8
+    two = np.where((r["label"] == 1) & (r["info"][:, 8] == 0))[0][:200]
+    res = [split_residual_max(w, m, r["x"][m], r["y"][m]) for m in two]
+    assert max(res) < FUG_TOL
+    m = two[0]
+    y = r["y"][m].copy()
+    y[0] *= 1 + 1e-6
+    y /= y.sum()
+    assert split_residual_max(w, m, r["x"][m], y) > FUG_TOL
