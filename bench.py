@@ -184,8 +184,8 @@ def main():
         idx = np.sort(np.random.Generator(np.random.PCG64(123)).choice(w.n, min(args.check, w.n),
                                                                        replace=False))
         o = oracle.flash(w.subset(idx), threads=min(16, os.cpu_count() or 1), want_min_tpd=1)
-        rep = compare(gg, o, idx, verbose=False)
-        rec["parity"] = {k: rep[k] for k in ("n", "label_mismatch", "value_mismatch",
+        rep = compare(gg, o, idx, verbose=False, w=w)
+        rec["parity"] = {k: rep[k] for k in ("n", "label_mismatch", "value_mismatch", "ref_unconverged",
                                              "single_mismatch", "max_err", "ss_path_agree")}
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)

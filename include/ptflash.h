@@ -192,6 +192,46 @@ int ptflash_eval_phase(int64_t n, int32_t nc, const double *c, const double *T,
                        const double *omega, const double *kij, double *lnphi,
                        double *Z, double *phi, hipStream_t stream);
 
+/* A batch of mixtures with different component counts, each with its own
+ * component set (packed, mixture-major).  Mixture m has nc_of[m] components
+ * (2 <= nc_of[m] <= ptflash_max_nc()); its rows start at off[m] in z, Tc,
+ * Pc, omega and in the outputs x, y (off[m+1] - off[m] = nc_of[m]), and its
+ * nc_of[m]^2 block of k_ij (row-major, symmetric, zero diagonal) starts at
+ * koff[m].  T and P hold one value per mixture.  nc_of, off (n+1 values)
+ * and koff (n values) are device arrays like the rest. */
+typedef struct {
+    int64_t n;
+    const int32_t *nc_of;   /* n      */
+    const int64_t *off;     /* n + 1  */
+    const int64_t *koff;    /* n      */
+    const double *z;        /* off[n] */
+    const double *T;        /* n      */
+    const double *P;        /* n      */
+    const double *Tc;       /* off[n] */
+    const double *Pc;       /* off[n] */
+    const double *omega;    /* off[n] */
+    const double *kij;      /* sum of nc_of[m]^2 */
+} ptflash_ragged_problem;
+
+/* Bytes of device workspace ptflash_flash_ragged needs (depends on n and
+ * the form only). */
+size_t ptflash_ragged_workspace_bytes(const ptflash_ragged_problem *prob,
+                                      const ptflash_options *opt);
+
+/* The flash of a ragged batch (the method of ptflash_flash applied to every
+ * mixture with its own nc and component set).  The mixtures are grouped by
+ * nc on the device (counting sort into per-nc id lists), each group is
+ * gathered into a contiguous uniform-nc batch in the workspace, flashed in
+ * the selected form, and its outputs are scattered back: label, beta, iters,
+ * status and flops per mixture, x and y at off[m].  res->factor must be
+ * NULL (keep_factor is not supported here).  Mixtures with nc_of[m] outside
+ * [2, ptflash_max_nc()] or a row count off[m+1] - off[m] != nc_of[m] are
+ * reported INVALID (label 0, beta = -1, x = y = the raw z row).  The call
+ * synchronises the stream once, to read the group sizes. */
+int ptflash_flash_ragged(const ptflash_ragged_problem *prob, const ptflash_options *opt,
+                         ptflash_result *res, void *workspace, size_t ws_bytes,
+                         hipStream_t stream);
+
 /* Text for a return code (static storage). */
 const char *ptflash_strerror(int code);
 

@@ -4,6 +4,8 @@ The compute path is the HIP library built from ``csrc/`` (C ABI in
 ``include/ptflash.h``); this package only binds it to PyTorch tensors.
 """
 from . import _capi  # noqa: F401
-from .api import FlashResult, eval_phase, flash, flash_autograd, flash_backward  # noqa: F401
+from .api import (FlashResult, eval_phase, flash, flash_autograd, flash_backward,  # noqa: F401
+                  flash_ragged)
 
-__all__ = ["flash", "flash_backward", "flash_autograd", "eval_phase", "FlashResult"]
+__all__ = ["flash", "flash_ragged", "flash_backward", "flash_autograd", "eval_phase",
+           "FlashResult"]

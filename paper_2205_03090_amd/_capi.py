@@ -18,7 +18,8 @@ ST = dict(INVALID=0x0001, SHORTCUT=0x0002, SA_RAN=0x0004, SA_UNCONV=0x0008,
           SPLIT_FAILED=0x0080, RR_NO_ROOT=0x0100, SWAPPED=0x0200, STEP_CAP=0x0400)
 EXPORTS = ["ptflash_default_options", "ptflash_max_nc", "ptflash_workspace_bytes",
            "ptflash_flash", "ptflash_flash_backward", "ptflash_backward_workspace_bytes",
-           "ptflash_eval_phase", "ptflash_strerror"]
+           "ptflash_eval_phase", "ptflash_strerror", "ptflash_ragged_workspace_bytes",
+           "ptflash_flash_ragged"]
 
 _vp = C.c_void_p
 
@@ -27,6 +28,12 @@ class Problem(C.Structure):
     _fields_ = [("n", C.c_int64), ("nc", C.c_int32), ("props_per_mixture", C.c_int32),
                 ("z", _vp), ("T", _vp), ("P", _vp), ("Tc", _vp), ("Pc", _vp),
                 ("omega", _vp), ("kij", _vp)]
+
+
+class RaggedProblem(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nc_of", _vp), ("off", _vp), ("koff", _vp), ("z", _vp),
+                ("T", _vp), ("P", _vp), ("Tc", _vp), ("Pc", _vp), ("omega", _vp),
+                ("kij", _vp)]
 
 
 class Options(C.Structure):
@@ -71,6 +78,12 @@ def lib():
         L.ptflash_flash_backward.restype = C.c_int
         L.ptflash_eval_phase.argtypes = [C.c_int64, C.c_int32] + [_vp] * 10 + [_vp]
         L.ptflash_eval_phase.restype = C.c_int
+        L.ptflash_ragged_workspace_bytes.argtypes = [C.POINTER(RaggedProblem),
+                                                     C.POINTER(Options)]
+        L.ptflash_ragged_workspace_bytes.restype = C.c_size_t
+        L.ptflash_flash_ragged.argtypes = [C.POINTER(RaggedProblem), C.POINTER(Options),
+                                           C.POINTER(Result), _vp, C.c_size_t, _vp]
+        L.ptflash_flash_ragged.restype = C.c_int
         L.ptflash_strerror.argtypes = [C.c_int]
         L.ptflash_strerror.restype = C.c_char_p
         _lib = L

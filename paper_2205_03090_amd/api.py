@@ -91,6 +91,45 @@ def flash(z, T, P, Tc, Pc, omega, kij, *, keep_factor: bool = False, stream=None
     return out
 
 
+def flash_ragged(z, T, P, nc_of, off, koff, Tc, Pc, omega, kij, *, stream=None, **opts):
+    """Flash of a ragged batch (mixtures with their own nc and component set,
+    packed as described for ptflash_ragged_problem): z, Tc, Pc, omega hold
+    off[n] values, kij the nc_of[m]^2 blocks at koff[m].  Returns a
+    FlashResult whose x and y are packed like z."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    z, T, P, Tc, Pc, omega, kij = (_f64(a, dev) for a in (z, T, P, Tc, Pc, omega, kij))
+    nc_of = torch.as_tensor(nc_of, dtype=torch.int32, device=dev).contiguous()
+    off = torch.as_tensor(off, dtype=torch.int64, device=dev).contiguous()
+    koff = torch.as_tensor(koff, dtype=torch.int64, device=dev).contiguous()
+    n = T.shape[0]
+    tot = z.shape[0]
+    o = _capi.default_options(**opts)
+    prob = _capi.RaggedProblem(n=n, nc_of=_ptr(nc_of).value, off=_ptr(off).value,
+                               koff=_ptr(koff).value, z=_ptr(z).value, T=_ptr(T).value,
+                               P=_ptr(P).value, Tc=_ptr(Tc).value, Pc=_ptr(Pc).value,
+                               omega=_ptr(omega).value, kij=_ptr(kij).value)
+    out = FlashResult(
+        label=torch.empty(n, dtype=torch.int8, device=dev),
+        beta=torch.empty(n, dtype=torch.float64, device=dev),
+        x=torch.empty(tot, dtype=torch.float64, device=dev),
+        y=torch.empty(tot, dtype=torch.float64, device=dev),
+        iters=torch.empty((n, _capi.NITERS), dtype=torch.int16, device=dev),
+        status=torch.empty(n, dtype=torch.int16, device=dev),
+        flops=torch.empty(n, dtype=torch.int32, device=dev),
+        factor=None)
+    res = _capi.Result(label=_ptr(out.label).value, beta=_ptr(out.beta).value,
+                       x=_ptr(out.x).value, y=_ptr(out.y).value, iters=_ptr(out.iters).value,
+                       status=_ptr(out.status).value, flops=_ptr(out.flops).value, factor=None)
+    L = _capi.lib()
+    ws_bytes = L.ptflash_ragged_workspace_bytes(C.byref(prob), C.byref(o))
+    ws = _workspace(ws_bytes, dev)
+    rc = L.ptflash_flash_ragged(C.byref(prob), C.byref(o), C.byref(res), _ptr(ws), ws_bytes,
+                                _stream_handle(stream))
+    _capi.check(rc, "ptflash_flash_ragged")
+    out._keepalive = (z, T, P, nc_of, off, koff, Tc, Pc, omega, kij, ws)
+    return out
+
+
 def eval_phase(c, T, P, Tc, Pc, omega, kij, *, derivs: bool = True, stream=None):
     """ln phi (n, nc), Z (n,) and Phi = n d ln phi/d n (n, nc, nc) of the SRK
     phase model at compositions c (n, nc)."""

@@ -1,6 +1,12 @@
-"""Builds the gfx950 HIP library in-tree with hipcc."""
+"""Builds the gfx950 HIP library in-tree with hipcc.
+
+The flash kernels are instantiated per component count: `csrc/flash_nc.hip`
+is compiled once for every nc in [2, MAX_NC] (in parallel), `csrc/ptflash.hip`
+holds the C ABI, and the objects are linked into `lib/libptflash.so`.
+"""
 from __future__ import annotations
 
+import concurrent.futures as cf
 import os
 import subprocess
 import sys
@@ -9,25 +15,60 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "lib")
+OBJDIR = os.path.join(LIBDIR, "obj")
 LIB = os.path.join(LIBDIR, "libptflash.so")
-MAX_NC = 12
-SOURCES = ["ptflash.hip"]
+MIN_NC = 2
+MAX_NC = 20
+
+ARCH = "gfx950"
+FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+         # no packed FP32 instructions in generated code
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         f"-DPTF_MAX_NC={MAX_NC}", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
-def hipcc_command(out: str) -> list[str]:
-    return ["hipcc", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            f"-DPTF_MAX_NC={MAX_NC}", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-            *[os.path.join(CSRC, s) for s in SOURCES], "-o", out]
+def _jobs() -> int:
+    env = os.environ.get("MAX_JOBS")
+    if env and env.isdigit():
+        return max(1, int(env))
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def compile_commands() -> list[tuple[list[str], str]]:
+    """(command, object) for every translation unit."""
+    cmds = []
+    for nc in range(MIN_NC, MAX_NC + 1):
+        obj = os.path.join(OBJDIR, f"flash_nc{nc}.o")
+        cmds.append((["hipcc", *FLAGS, f"-DPTF_NC={nc}", "-c",
+                      os.path.join(CSRC, "flash_nc.hip"), "-o", obj], obj))
+    obj = os.path.join(OBJDIR, "ptflash.o")
+    cmds.append((["hipcc", *FLAGS, "-c", os.path.join(CSRC, "ptflash.hip"), "-o", obj], obj))
+    return cmds
 
 
 def build(verbose: bool = False) -> str:
-    os.makedirs(LIBDIR, exist_ok=True)
+    os.makedirs(OBJDIR, exist_ok=True)
+    cmds = compile_commands()
+
+    def run(cmd_obj):
+        cmd, obj = cmd_obj
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {obj}:\n{r.stderr}")
+        return obj
+
+    # the large component counts take longest: start them first
+    order = sorted(cmds, key=lambda c: -int(c[1].rsplit("nc", 1)[-1][:-2])
+                   if "flash_nc" in c[1] else 0)
+    with cf.ThreadPoolExecutor(_jobs()) as ex:
+        objs = list(ex.map(run, order))
     tmp = LIB + ".tmp"
-    cmd = hipcc_command(tmp)
+    link = ["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+        print(" ".join(link), flush=True)
+    subprocess.run(link, check=True)
     os.replace(tmp, LIB)
     return LIB
 

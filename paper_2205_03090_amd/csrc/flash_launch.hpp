@@ -1,0 +1,589 @@
+// flash_launch.hpp -- kernels of the flash and their host-side launchers for
+// one component count.  Included only by flash_nc.hip, which is compiled
+// once per nc and instantiates the nc_* entry points declared in
+// flash_api.hpp; everything else here has internal linkage.
+//
+// The flash runs as a pipeline of stage kernels (flash_stages.hpp): every
+// stage is a persistent grid whose wavefronts take work items (mixtures or
+// stability trials) from a device list, one item per lane, and refill a lane
+// as soon as its item finishes; an item that needs a later stage is appended
+// to that stage's list.  This is the paper's synchronizer (save converged
+// rows, drop them from the active set) and its barrier per stage (Sec. 3,
+// Algorithm 1), done on the device without host synchronisation: the kernel
+// order on the stream is the barrier.  The plain form runs the same items
+// one step per launch, with compaction and a host read of the active count
+// after every launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "flash_api.hpp"
+#include "flash_stages.hpp"
+#include "adjoint_device.hpp"
+
+namespace ptf {
+namespace {
+
+constexpr int kBlock = 256;
+
+__global__ void reset_counters(unsigned long long *q, int n)
+{
+    if ((int)threadIdx.x < n) q[threadIdx.x] = 0ull;
+}
+
+// Number of items of a stage: all mixtures for the first stage, else the
+// length of the stage's list (written by the previous stages).
+template <class Item, int NC>
+__device__ __forceinline__ int64_t stage_count(const Ctx<NC> &c)
+{
+    return Item::LIST < 0 ? c.a.n : (int64_t)c.L.count[Item::LIST];
+}
+
+template <class Item, int NC>
+__device__ __forceinline__ uint32_t stage_id(const Ctx<NC> &c, int64_t k)
+{
+    return Item::LIST < 0 ? (uint32_t)k : c.L.ids[Item::LIST < 0 ? 0 : Item::LIST][k];
+}
+
+// Ids a wavefront claims from a stage's input with one atomic.
+constexpr int kChunk = 64;
+// Per-wavefront staging of list appends in LDS (entries per list).
+constexpr int kStage = 128;
+constexpr int kWavesPerBlock = kBlock / 64;
+
+// Wave-level helpers (called by all 64 lanes together).
+__device__ __forceinline__ unsigned long long lanes_below(int lane)
+{
+    return (1ull << lane) - 1ull;
+}
+
+__device__ __forceinline__ unsigned long long bcast64(unsigned long long v, int src)
+{
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, src);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), src);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Copies a wavefront's staged entries of one list to the global list: one
+// atomic for the whole batch, then a coalesced copy.
+__device__ __forceinline__ void flush_list(const Lists &L, int list, const uint32_t *buf,
+                                           int fill, int lane)
+{
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(&L.count[list], (unsigned long long)fill);
+    base = bcast64(base, 0);
+    for (int k = lane; k < fill; k += 64) L.ids[list][base + (unsigned long long)k] = buf[k];
+}
+
+// Stages the entries of one outbox slot (list l, first id i, n ids) of every
+// lane whose slot names `list`.
+__device__ __forceinline__ void stage_slot(const Lists &L, int list, int l, uint32_t i, int n,
+                                           uint32_t *buf, int &fill, int lane)
+{
+    const bool mine = (l == list);
+    const unsigned long long m1 = __ballot(mine);
+    if (m1 == 0ull) return;
+    const unsigned long long m2 = __ballot(mine && n == 2);
+    const int tot = __popcll(m1) + __popcll(m2);
+    if (fill + tot > kStage) {
+        flush_list(L, list, buf, fill, lane);
+        fill = 0;
+    }
+    if (mine) {
+        const unsigned long long b = lanes_below(lane);
+        const int r = fill + __popcll(m1 & b) + __popcll(m2 & b);
+        buf[r] = i;
+        if (n == 2) buf[r + 1] = i + 1u;
+    }
+    fill += tot;
+}
+
+// Persistent stage: one item per lane; lanes whose item finished take the
+// next ids of the wavefront's claimed chunk (one atomic per kChunk ids), and
+// the list entries the steps produce are staged per wavefront in LDS and
+// appended kStage at a time (one atomic per batch).  Every item finishes
+// within its stage's iteration caps (and kStepGuard steps), so every
+// wavefront reaches the exit, where it appends what it still holds.
+template <class Item, int NC>
+__global__ void __launch_bounds__(kBlock)
+stage_persistent(Ctx<NC> c, const double *__restrict__ Tc, const double *__restrict__ Pc,
+                 const double *__restrict__ om, const double *__restrict__ K,
+                 unsigned long long *__restrict__ take)
+{
+    __shared__ uint32_t stage_buf[kWavesPerBlock][L_COUNT][kStage];
+    c.pr = Props{Tc, Pc, om, K};
+    const int64_t count = stage_count<Item, NC>(c);
+    const int lane = (int)__lane_id();
+    uint32_t(*buf)[kStage] = stage_buf[threadIdx.x / 64];
+    int fill[L_COUNT];
+#pragma unroll
+    for (int l = 0; l < L_COUNT; ++l) fill[l] = 0;
+    unsigned long long cb = 0, ce = 0;   // claimed, not yet taken: [cb, ce)
+    Item it;
+    bool live = false, gone = false;
+    for (;;) {
+        const bool want = !live && !gone;
+        const unsigned long long mask = __ballot(want);
+        if (mask) {
+            const int r = __popcll(mask);
+            const unsigned long long avail = ce - cb;
+            unsigned long long nb = 0;
+            if (avail < (unsigned long long)r) {
+                if (lane == 0) nb = atomicAdd(take, (unsigned long long)kChunk);
+                nb = bcast64(nb, 0);
+            }
+            if (want) {
+                const unsigned long long rank = (unsigned long long)__popcll(mask & lanes_below(lane));
+                const unsigned long long k = rank < avail ? cb + rank : nb + (rank - avail);
+                if ((int64_t)k < count) live = it.begin(c, stage_id<Item, NC>(c, (int64_t)k));
+                else gone = true;
+            }
+            if (avail < (unsigned long long)r) {
+                cb = nb + ((unsigned long long)r - avail);
+                ce = nb + kChunk;
+            } else {
+                cb += (unsigned long long)r;
+            }
+        }
+        if (__ballot(!gone) == 0ull) break;
+        it.ob.clear();
+        if (live) live = !it.step(c);
+#pragma unroll
+        for (int l = 0; l < L_COUNT; ++l) {
+            stage_slot(c.L, l, it.ob.l0, it.ob.i0, it.ob.n0, buf[l], fill[l], lane);
+            stage_slot(c.L, l, it.ob.l1, it.ob.i1, 1, buf[l], fill[l], lane);
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < L_COUNT; ++l)
+        if (fill[l] > 0) flush_list(c.L, l, buf[l], fill[l], lane);
+}
+
+// Plain form: begin every item of the stage and list the live ones ...
+template <class Item, int NC>
+__global__ void __launch_bounds__(kBlock)
+stage_plain_begin(Ctx<NC> c, const double *__restrict__ Tc, const double *__restrict__ Pc,
+                  const double *__restrict__ om, const double *__restrict__ K, Item *states,
+                  uint32_t *active, unsigned long long *nactive)
+{
+    c.pr = Props{Tc, Pc, om, K};
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= stage_count<Item, NC>(c)) return;
+    Item it;
+    if (it.begin(c, stage_id<Item, NC>(c, k))) {
+        states[k] = it;
+        active[atomicAdd(nactive, 1ull)] = (uint32_t)k;
+    }
+}
+
+// ... then one step of every live item per launch, listing those still live
+// (the list order does not matter: each item's result depends on its own
+// state only).
+template <class Item, int NC>
+__global__ void __launch_bounds__(kBlock)
+stage_plain_step(Ctx<NC> c, const double *__restrict__ Tc, const double *__restrict__ Pc,
+                 const double *__restrict__ om, const double *__restrict__ K, Item *states,
+                 const uint32_t *__restrict__ active, int64_t nact, uint32_t *next,
+                 unsigned long long *nnext)
+{
+    c.pr = Props{Tc, Pc, om, K};
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nact) return;
+    const uint32_t k = active[j];
+    Item it = states[k];
+    it.ob.clear();
+    const bool done = it.step(c);
+    push_outbox(c.L, it.ob);
+    if (!done) {
+        states[k] = it;
+        next[atomicAdd(nnext, 1ull)] = k;
+    }
+}
+
+// Diagnostic: ln phi, Z and the full Phi matrix at given compositions.
+template <int NC>
+__global__ void __launch_bounds__(kBlock)
+eval_phase_kernel(int64_t n, const double *__restrict__ c, const double *__restrict__ T,
+                  const double *__restrict__ P, const double *__restrict__ Tc,
+                  const double *__restrict__ Pc, const double *__restrict__ om,
+                  const double *__restrict__ K, double *lnphi, double *Zo, double *phi)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    Eos<NC> e;
+    eos_setup<NC>(e, Tc, Pc, om, T[m], P[m]);
+    double w[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) w[i] = c[m * NC + i];
+    Phase<NC> o;
+    uint32_t fl = 0;
+    phase_eval<NC>(o, e, K, w, fl);
+#pragma unroll
+    for (int i = 0; i < NC; ++i) lnphi[m * NC + i] = o.lnphi[i];
+    Zo[m] = o.Z;
+    if (phi) {
+        double F[Tri<NC>::N];
+        phase_derivs<NC>(F, o, e, K, fl);
+#pragma unroll
+        for (int i = 0; i < NC; ++i)
+#pragma unroll
+            for (int j = 0; j <= i; ++j) {
+                phi[m * NC * NC + i * NC + j] = F[tri(i, j)];
+                phi[m * NC * NC + j * NC + i] = F[tri(i, j)];
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Backward (implicit function theorem on the converged split)
+// ---------------------------------------------------------------------------
+
+
+template <int NC, bool PM>
+__global__ void __launch_bounds__(kBlock)
+flash_backward_kernel(BwdArgs a, const double *__restrict__ Tc0, const double *__restrict__ Pc0,
+                      const double *__restrict__ om0, const double *__restrict__ K0)
+{
+    constexpr int NP = Tri<NC>::N;
+    constexpr int NQ = NC * (NC - 1) / 2;
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= a.n) return;
+    const Props pp = mix_props<NC, PM>(Props{Tc0, Pc0, om0, K0}, m);
+    const double *__restrict__ Tc = pp.Tc;
+    const double *__restrict__ Pc = pp.Pc;
+    const double *__restrict__ om = pp.om;
+    const double *__restrict__ K = pp.K;
+    double zt[NC], s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NC; ++i) { zt[i] = a.z[m * NC + i]; s += zt[i]; }
+#pragma unroll
+    for (int i = 0; i < NC; ++i) zt[i] /= s;
+    const uint16_t st = a.status ? a.status[m] : (uint16_t)0;
+    double ztb[NC], gT = 0.0, gP = 0.0;
+    double gkq[NQ > 0 ? NQ : 1];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) gkq[q] = 0.0;
+    bool bad = (st & (kStInvalid | kStSplitUnconv | kStStepCap)) != 0;
+    if (!bad && a.label[m] == 1) {
+        const double T = a.T[m], P = a.P[m], beta = a.beta[m];
+        double x[NC], y[NC], gx[NC], gy[NC];
+        double gxx = 0.0, gyy = 0.0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            x[i] = a.x[m * NC + i];
+            y[i] = a.y[m * NC + i];
+            gx[i] = a.gx[m * NC + i];
+            gy[i] = a.gy[m * NC + i];
+            gxx += gx[i] * x[i];
+            gyy += gy[i] * y[i];
+        }
+        const double gb = a.gb[m];
+        // u_bar = (do/du)^T o_bar for o = (beta = sum u, y = u/beta,
+        // x = (z~ - u)/(1 - beta))
+        double lam[NC];
+        const double ib = 1.0 / beta, il = 1.0 / (1.0 - beta);
+#pragma unroll
+        for (int j = 0; j < NC; ++j) lam[j] = gb + (gy[j] - gyy) * ib - (gx[j] - gxx) * il;
+        // H~ lambda = u_bar with the forward's factor H~ = L L^T
+        double Lf[NP], dinv[NC], tmp[NC];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) Lf[k] = a.factor[m * NP + k];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) dinv[i] = 1.0 / Lf[tri(i, i)];
+        lower_solve<NC>(tmp, Lf, dinv, lam);
+        upper_solve<NC>(lam, Lf, dinv, tmp);
+        bad = !isfinite(lam[0]);
+        // phase data at the solution
+        Eos<NC> e;
+        eos_setup<NC>(e, Tc, Pc, om, T, P);
+        uint32_t fl = 0;
+        Phase<NC> oL, oV;
+        phase_eval<NC>(oL, e, K, x, fl);
+        double Phi[NP];
+        phase_derivs<NC>(Phi, oL, e, K, fl);
+        // z~_bar_j = [gx_j + lambda_j/x_j - sum lambda + (Phi^L lambda)_j]/(1 - beta)
+        double sl = 0.0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) sl += lam[i];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            double pl = 0.0;
+#pragma unroll
+            for (int i = 0; i < NC; ++i) pl += Phi[i >= j ? tri(i, j) : tri(j, i)] * lam[i];
+            ztb[j] = (gx[j] + lam[j] / x[j] - sl + pl) * il;
+        }
+        PhaseGrad<NC> gL, gV;
+        phase_param_vjp<NC>(gL, oL, e, x, lam, K, Tc, om, T, P);
+        phase_eval<NC>(oV, e, K, y, fl);
+        phase_param_vjp<NC>(gV, oV, e, y, lam, K, Tc, om, T, P);
+        gT = -(gV.dT - gL.dT);
+        gP = -(gV.dP - gL.dP);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) gkq[q] = -(gV.dk[q] - gL.dk[q]);
+    } else if (!bad) {
+        // single phase: x = y = z~
+#pragma unroll
+        for (int i = 0; i < NC; ++i) ztb[i] = a.gx[m * NC + i] + a.gy[m * NC + i];
+    }
+    if (bad) {
+        const double nan = __builtin_nan("");
+#pragma unroll
+        for (int i = 0; i < NC; ++i) ztb[i] = nan;
+        gT = gP = nan;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) gkq[q] = nan;
+    }
+    // through the normalisation z~ = z / sum z
+    double zz = 0.0;
+#pragma unroll
+    for (int i = 0; i < NC; ++i) zz += ztb[i] * zt[i];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) a.gz[m * NC + j] = (ztb[j] - zz) / s;
+    a.gT[m] = gT;
+    a.gP[m] = gP;
+    if (a.gk) {
+        int q = 0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) a.gk[m * NC * NC + i * NC + i] = bad ? gT /* NaN */ : 0.0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i)
+#pragma unroll
+            for (int j = i + 1; j < NC; ++j, ++q) {
+                a.gk[m * NC * NC + i * NC + j] = 0.5 * gkq[q];
+                a.gk[m * NC * NC + j * NC + i] = 0.5 * gkq[q];
+            }
+    }
+    if (a.kpart) {
+        // unconverged mixtures (NaN above) do not enter the batch sum
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) a.kpart[(int64_t)q * a.n + m] = bad ? 0.0 : gkq[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+int device_cus()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return cus;
+}
+
+
+// Workspace: counters | per-mixture records | stage lists | (plain form:)
+// item states and two active lists.
+constexpr int kNumCounters = 16;   // L_COUNT list counts, 6 take counters, 2 plain
+constexpr int kTake0 = L_COUNT;
+constexpr int kPlain0 = L_COUNT + 6;
+
+template <int NC>
+size_t plain_state_bytes()
+{
+    size_t m = sizeof(PreItem<NC, false>);
+    m = m > sizeof(SaSsItem<NC, false>) ? m : sizeof(SaSsItem<NC, false>);
+    m = m > sizeof(SaTrItem<NC, false>) ? m : sizeof(SaTrItem<NC, false>);
+    m = m > sizeof(SaFinItem<NC, false>) ? m : sizeof(SaFinItem<NC, false>);
+    m = m > sizeof(SpSsItem<NC, false>) ? m : sizeof(SpSsItem<NC, false>);
+    m = m > sizeof(SpNtItem<NC, false>) ? m : sizeof(SpNtItem<NC, false>);
+    return m;
+}
+
+template <int NC>
+size_t workspace_bytes(int64_t n, int form)
+{
+    const size_t un = (size_t)n;
+    size_t b = 256 + align256(un * sizeof(MixRec<NC>)) + 3 * align256(2 * un * 4) +
+               3 * align256(un * 4);
+    if (form == PTFLASH_FORM_PLAIN)
+        b += align256(2 * un * plain_state_bytes<NC>()) + 2 * align256(2 * un * 4);
+    return b;
+}
+
+struct Carve {
+    char *p;
+    template <typename T>
+    T *take(size_t bytes)
+    {
+        T *r = (T *)p;
+        p += align256(bytes);
+        return r;
+    }
+};
+
+template <int NC>
+void setup_ctx(Ctx<NC> &c, const FlashArgs &a, int64_t n, void *ws, char **tail)
+{
+    Carve cv{(char *)ws};
+    c.a = a;
+    c.pr = Props{nullptr, nullptr, nullptr, nullptr};
+    unsigned long long *cnt = cv.take<unsigned long long>(256);
+    c.rec = cv.take<MixRec<NC>>((size_t)n * sizeof(MixRec<NC>));
+    c.L.ids[L_SA] = cv.take<uint32_t>(2 * (size_t)n * 4);
+    c.L.ids[L_SATR] = cv.take<uint32_t>(2 * (size_t)n * 4);
+    cv.take<uint32_t>(2 * (size_t)n * 4);   // spare (keeps the layout aligned to the size formula)
+    c.L.ids[L_SAFIN] = cv.take<uint32_t>((size_t)n * 4);
+    c.L.ids[L_SPLIT] = cv.take<uint32_t>((size_t)n * 4);
+    c.L.ids[L_NT] = cv.take<uint32_t>((size_t)n * 4);
+    c.L.count = cnt;
+    *tail = cv.p;
+}
+
+int grid_for(const void *kernel, int block, int requested)
+{
+    if (requested > 0) return requested;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess)
+        return -1;
+    const int cus = device_cus();
+    if (cus <= 0) return -1;
+    return (per_cu > 0 ? per_cu : 1) * cus;
+}
+
+template <class Item, int NC>
+int run_persistent_stage(const Ctx<NC> &c, const ptflash_problem *p,
+                                const ptflash_options *o, int take_slot, hipStream_t s)
+{
+    const int block = o->block > 0 ? o->block : kBlock;
+    if (block % 64 != 0 || block > kBlock) return PTFLASH_EINVAL;
+    const int grid = grid_for((const void *)stage_persistent<Item, NC>, block, o->grid);
+    if (grid <= 0) return PTFLASH_EHIP;
+    hipLaunchKernelGGL((stage_persistent<Item, NC>), dim3(grid), dim3(block), 0, s, c, p->Tc,
+                       p->Pc, p->omega, p->kij, c.L.count + take_slot);
+    return hipGetLastError() == hipSuccess ? PTFLASH_OK : PTFLASH_EHIP;
+}
+
+template <int NC, bool PM>
+int launch_persistent(const FlashArgs &a, const ptflash_problem *p, const ptflash_options *o,
+                      void *ws, hipStream_t s)
+{
+    Ctx<NC> c;
+    char *tail;
+    setup_ctx<NC>(c, a, p->n, ws, &tail);
+    hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, c.L.count, kNumCounters);
+    int rc;
+    if ((rc = run_persistent_stage<PreItem<NC, PM>, NC>(c, p, o, kTake0 + 0, s))) return rc;
+    if ((rc = run_persistent_stage<SaSsItem<NC, PM>, NC>(c, p, o, kTake0 + 1, s))) return rc;
+    if ((rc = run_persistent_stage<SaTrItem<NC, PM>, NC>(c, p, o, kTake0 + 2, s))) return rc;
+    if ((rc = run_persistent_stage<SaFinItem<NC, PM>, NC>(c, p, o, kTake0 + 3, s))) return rc;
+    if ((rc = run_persistent_stage<SpSsItem<NC, PM>, NC>(c, p, o, kTake0 + 4, s))) return rc;
+    if ((rc = run_persistent_stage<SpNtItem<NC, PM>, NC>(c, p, o, kTake0 + 5, s))) return rc;
+    return PTFLASH_OK;
+}
+
+// Reads a device counter after the work queued so far (host sync).
+int read_count(const unsigned long long *dcnt, int64_t &out, hipStream_t s)
+{
+    unsigned long long h = 0;
+    if (hipGetLastError() != hipSuccess) return PTFLASH_EHIP;
+    if (hipMemcpyAsync(&h, dcnt, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return PTFLASH_EHIP;
+    out = (int64_t)h;
+    return PTFLASH_OK;
+}
+
+template <class Item, int NC>
+int run_plain_stage(const Ctx<NC> &c, const ptflash_problem *p, char *tail, hipStream_t s)
+{
+    const int64_t n = p->n;
+    Carve cv{tail};
+    Item *states = cv.take<Item>(2 * (size_t)n * plain_state_bytes<NC>());
+    uint32_t *la = cv.take<uint32_t>(2 * (size_t)n * 4);
+    uint32_t *lb = cv.take<uint32_t>(2 * (size_t)n * 4);
+    unsigned long long *na = c.L.count + kPlain0, *nb = c.L.count + kPlain0 + 1;
+    int64_t count = n;
+    int rc;
+    if (Item::LIST >= 0 && (rc = read_count(c.L.count + Item::LIST, count, s))) return rc;
+    if (count == 0) return PTFLASH_OK;
+    auto grid = [](int64_t k) { return dim3((unsigned)((k + kBlock - 1) / kBlock)); };
+    hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, na, 1);
+    hipLaunchKernelGGL((stage_plain_begin<Item, NC>), grid(count), dim3(kBlock), 0, s, c, p->Tc,
+                       p->Pc, p->omega, p->kij, states, la, na);
+    int64_t nact = 0;
+    if ((rc = read_count(na, nact, s))) return rc;
+    for (int guard = 0; nact > 0 && guard <= kStepGuard + 1; ++guard) {
+        hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, nb, 1);
+        hipLaunchKernelGGL((stage_plain_step<Item, NC>), grid(nact), dim3(kBlock), 0, s, c, p->Tc,
+                           p->Pc, p->omega, p->kij, states, la, nact, lb, nb);
+        if ((rc = read_count(nb, nact, s))) return rc;
+        uint32_t *t = la; la = lb; lb = t;
+        unsigned long long *tc = na; na = nb; nb = tc;
+    }
+    return PTFLASH_OK;
+}
+
+template <int NC, bool PM>
+int launch_plain(const FlashArgs &a, const ptflash_problem *p, void *ws, hipStream_t s)
+{
+    Ctx<NC> c;
+    char *tail;
+    setup_ctx<NC>(c, a, p->n, ws, &tail);
+    hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, c.L.count, kNumCounters);
+    int rc;
+    if ((rc = run_plain_stage<PreItem<NC, PM>, NC>(c, p, tail, s))) return rc;
+    if ((rc = run_plain_stage<SaSsItem<NC, PM>, NC>(c, p, tail, s))) return rc;
+    if ((rc = run_plain_stage<SaTrItem<NC, PM>, NC>(c, p, tail, s))) return rc;
+    if ((rc = run_plain_stage<SaFinItem<NC, PM>, NC>(c, p, tail, s))) return rc;
+    if ((rc = run_plain_stage<SpSsItem<NC, PM>, NC>(c, p, tail, s))) return rc;
+    if ((rc = run_plain_stage<SpNtItem<NC, PM>, NC>(c, p, tail, s))) return rc;
+    return PTFLASH_OK;
+}
+
+template <int NC>
+int launch_eval(int64_t n, const double *c, const double *T, const double *P,
+                       const double *Tc, const double *Pc, const double *om, const double *K,
+                       double *lnphi, double *Z, double *phi, hipStream_t s)
+{
+    const int64_t blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > 0)
+        hipLaunchKernelGGL(eval_phase_kernel<NC>, dim3((unsigned)blocks), dim3(kBlock), 0, s, n,
+                           c, T, P, Tc, Pc, om, K, lnphi, Z, phi);
+    return hipGetLastError() == hipSuccess ? PTFLASH_OK : PTFLASH_EHIP;
+}
+
+}  // namespace
+
+template <int NC>
+size_t nc_workspace_bytes(int64_t n, int form)
+{
+    return workspace_bytes<NC>(n, form);
+}
+
+template <int NC>
+int nc_flash(const FlashArgs &a, const ptflash_problem *p, const ptflash_options *o, void *ws,
+             hipStream_t s)
+{
+    if (o->form == PTFLASH_FORM_PLAIN)
+        return p->props_per_mixture ? launch_plain<NC, true>(a, p, ws, s)
+                                    : launch_plain<NC, false>(a, p, ws, s);
+    return p->props_per_mixture ? launch_persistent<NC, true>(a, p, o, ws, s)
+                                : launch_persistent<NC, false>(a, p, o, ws, s);
+}
+
+template <int NC>
+int nc_backward(const BwdArgs &b, const ptflash_problem *p, hipStream_t s)
+{
+    const unsigned nb = (unsigned)((p->n + kBlock - 1) / kBlock);
+    if (p->props_per_mixture)
+        hipLaunchKernelGGL((flash_backward_kernel<NC, true>), dim3(nb), dim3(kBlock), 0, s, b,
+                           p->Tc, p->Pc, p->omega, p->kij);
+    else
+        hipLaunchKernelGGL((flash_backward_kernel<NC, false>), dim3(nb), dim3(kBlock), 0, s, b,
+                           p->Tc, p->Pc, p->omega, p->kij);
+    return hipGetLastError() == hipSuccess ? PTFLASH_OK : PTFLASH_EHIP;
+}
+
+template <int NC>
+int nc_eval(int64_t n, const double *c, const double *T, const double *P, const double *Tc,
+            const double *Pc, const double *om, const double *K, double *lnphi, double *Z,
+            double *phi, hipStream_t s)
+{
+    return launch_eval<NC>(n, c, T, P, Tc, Pc, om, K, lnphi, Z, phi, s);
+}
+
+}  // namespace ptf

@@ -35,6 +35,7 @@
 //     below tol_polish, and y is chosen as the phase with the larger Z.
 #pragma once
 
+#include "flash_api.hpp"
 #include "srk_device.hpp"
 
 namespace ptf {
@@ -71,20 +72,6 @@ struct MixRec {
     int16_t it[8];
 };
 
-// Kernel arguments shared by every stage.
-struct FlashArgs {
-    int64_t n;
-    const double *z, *T, *P;
-    int max_pre_ss, max_ss, max_tr_sa, max_tr_split, max_polish, dem_every;
-    int keep_factor;
-    double tol_sa_ss, tol_sa_tr, tol_split_ss, tol_split_tr, tol_polish, eps_tm;
-    int8_t *label;
-    double *beta, *x, *y;
-    int16_t *iters;
-    uint16_t *status;
-    uint32_t *flops;
-    double *factor;
-};
 
 // Work lists: ids (mixture m, or trial 2m + t) and their counts.
 enum ListId : int { L_SA = 0, L_SATR = 1, L_SAFIN = 2, L_SPLIT = 3, L_NT = 4, L_COUNT = 5 };
@@ -111,10 +98,59 @@ struct Ctx {
     Lists L;
 };
 
+// Component set of mixture m: the shared set (wave-uniform loads), or, with
+// one set per mixture (PM), the mixture's own rows (nc values each, nc*nc k).
+template <int NC, bool PM>
+__device__ __forceinline__ Props mix_props(const Props &pr, int64_t m)
+{
+    if constexpr (!PM) {
+        return pr;
+    } else {
+        return Props{pr.Tc + m * NC, pr.Pc + m * NC, pr.om + m * NC, pr.K + m * NC * NC};
+    }
+}
+
 __device__ __forceinline__ void push(const Lists &L, int list, uint32_t id)
 {
     const unsigned long long k = atomicAdd(&L.count[list], 1ull);
     L.ids[list][k] = id;
+}
+
+// What one step of an item hands to later stages: at most two list entries,
+// the first of which may be a pair of consecutive ids (the two stability
+// trials 2m, 2m + 1 of a mixture).  The stage kernel appends them to the
+// lists after the step, so that the appends of a wavefront can be batched.
+struct Outbox {
+    int l0, l1;      // list of each slot, -1 when empty
+    int n0;          // ids in slot 0: 1, or 2 for a trial pair
+    uint32_t i0, i1; // first id of each slot
+    __device__ __forceinline__ void clear()
+    {
+        l0 = -1;
+        l1 = -1;
+        n0 = 1;
+    }
+    __device__ __forceinline__ void put(int list, uint32_t id)
+    {
+        if (l0 < 0) { l0 = list; i0 = id; n0 = 1; }
+        else { l1 = list; i1 = id; }
+    }
+    __device__ __forceinline__ void put_pair(int list, uint32_t id)
+    {
+        l0 = list;
+        i0 = id;
+        n0 = 2;
+    }
+};
+
+// Appends an outbox directly (one atomic per entry; the plain form).
+__device__ __forceinline__ void push_outbox(const Lists &L, const Outbox &ob)
+{
+    if (ob.l0 >= 0) {
+        push(L, ob.l0, ob.i0);
+        if (ob.n0 == 2) push(L, ob.l0, ob.i0 + 1u);
+    }
+    if (ob.l1 >= 0) push(L, ob.l1, ob.i1);
 }
 
 // ---------------------------------------------------------------------------
@@ -212,8 +248,9 @@ __device__ __forceinline__ double ss_update(double (&v)[NC], double (&prev)[NC],
 // ---------------------------------------------------------------------------
 // Pre: feed, Wilson, three substitutions, triage (Sec. 2.2.3)
 // ---------------------------------------------------------------------------
-template <int NC>
+template <int NC, bool PM>
 struct PreItem {
+    Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = -1;   // input: mixtures 0..n-1
     int64_t m;
     double T, P;
@@ -228,6 +265,7 @@ struct PreItem {
     {
         const FlashArgs &a = c.a;
         m = id;
+        const Props pp = mix_props<NC, PM>(c.pr, m);
         T = a.T[m];
         P = a.P[m];
         fl = 0;
@@ -245,10 +283,10 @@ struct PreItem {
         }
 #pragma unroll
         for (int i = 0; i < NC; ++i) {
-            ok = ok && (c.pr.Tc[i] > 0.0) && (c.pr.Pc[i] > 0.0) && isfinite(c.pr.om[i]);
-            ok = ok && (c.pr.K[i * NC + i] == 0.0);
+            ok = ok && (pp.Tc[i] > 0.0) && (pp.Pc[i] > 0.0) && isfinite(pp.om[i]);
+            ok = ok && (pp.K[i * NC + i] == 0.0);
 #pragma unroll
-            for (int j = 0; j < i; ++j) ok = ok && (c.pr.K[i * NC + j] == c.pr.K[j * NC + i]);
+            for (int j = 0; j < i; ++j) ok = ok && (pp.K[i * NC + j] == pp.K[j * NC + i]);
         }
         if (!ok) {
             // invalid input: report the raw feed as a single phase
@@ -258,7 +296,7 @@ struct PreItem {
         }
 #pragma unroll
         for (int i = 0; i < NC; ++i) z[i] = z[i] / s;
-        eos_setup<NC>(e, c.pr.Tc, c.pr.Pc, c.pr.om, T, P);
+        eos_setup<NC>(e, pp.Tc, pp.Pc, pp.om, T, P);
         return true;
     }
 
@@ -286,11 +324,10 @@ struct PreItem {
         for (int k = 0; k < 8; ++k) r.it[k] = 0;
         r.it[0] = (int16_t)(phase - 1 < 0 ? 0 : phase - 1);
         if (to_split) {
-            push(c.L, L_SPLIT, (uint32_t)m);
+            ob.put(L_SPLIT, (uint32_t)m);
         } else {
-            push(c.L, L_SA, (uint32_t)(2 * m));
-            push(c.L, L_SA, (uint32_t)(2 * m + 1));
-            push(c.L, L_SAFIN, (uint32_t)m);
+            ob.put_pair(L_SA, (uint32_t)(2 * m));
+            ob.put(L_SAFIN, (uint32_t)m);
         }
     }
 
@@ -303,6 +340,7 @@ struct PreItem {
 
     __device__ __forceinline__ bool step(const Ctx<NC> &c)
     {
+        const Props pp = mix_props<NC, PM>(c.pr, m);
         const FlashArgs &a = c.a;
         double w0[NC], w1[NC];
         bool e1 = true;
@@ -313,22 +351,22 @@ struct PreItem {
         } else if (!(xy_from_lnk<NC>(w0, w1, lk, z, theta, fl) && theta > 0.0 && theta < 1.0)) {
             // case 1: the Rachford-Rice root left (0,1)
             double lkw[NC];
-            wilson(lkw, c.pr);
+            wilson(lkw, pp);
             fl += 5 * NC;
             route(c, false, kStSaRan, lkw);
             return true;
         }
         Phase<NC> o;
-        phase_eval<NC>(o, e, c.pr.K, w0, fl);
+        phase_eval<NC>(o, e, pp.K, w0, fl);
         double r0[NC];
 #pragma unroll
         for (int i = 0; i < NC; ++i) r0[i] = o.lnphi[i];
-        if (e1) phase_eval<NC>(o, e, c.pr.K, w1, fl);
+        if (e1) phase_eval<NC>(o, e, pp.K, w1, fl);
         if (phase == 0) {
 #pragma unroll
             for (int i = 0; i < NC; ++i) d[i] = log(z[i]) + r0[i];
             fl += 2 * NC;
-            wilson(lk, c.pr);
+            wilson(lk, pp);
             fl += 5 * NC;
             phase = 1;
             return false;
@@ -348,7 +386,7 @@ struct PreItem {
         const double dg = (1.0 - theta) * tx + theta * ty;
         fl += 8 * NC + 3;
         double lkw[NC];
-        wilson(lkw, c.pr);
+        wilson(lkw, pp);
         fl += 5 * NC;
         if (tx < -a.eps_tm || ty < -a.eps_tm || dg < -a.eps_tm) {
             theta = 0.5;
@@ -364,8 +402,9 @@ struct PreItem {
 // SaSs: successive substitution of one stability trial (Sec. 2.2.1, eq.
 // ss_analyser): ln W <- d - ln phi(W)
 // ---------------------------------------------------------------------------
-template <int NC>
+template <int NC, bool PM>
 struct SaSsItem {
+    Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_SA;
     int64_t m;
     int t;
@@ -406,18 +445,19 @@ struct SaSsItem {
         r.it[t == 0 ? 2 : 4] = 0;
         r.tfl[t] = fl;
         r.tst[t] = st;
-        if (to_tr) push(c.L, L_SATR, (uint32_t)(2 * m + t));
+        if (to_tr) ob.put(L_SATR, (uint32_t)(2 * m + t));
     }
 
     __device__ __forceinline__ bool step(const Ctx<NC> &c)
     {
+        const Props pp = mix_props<NC, PM>(c.pr, m);
         const FlashArgs &a = c.a;
         double W[NC];
 #pragma unroll
         for (int i = 0; i < NC; ++i) W[i] = exp(lw[i]);
         fl += NC;
         Phase<NC> o;
-        phase_eval<NC>(o, e, c.pr.K, W, fl);
+        phase_eval<NC>(o, e, pp.K, W, fl);
         double grad[NC], tm = 1.0, gmax = 0.0;
 #pragma unroll
         for (int i = 0; i < NC; ++i) {
@@ -461,8 +501,9 @@ struct SaSsItem {
 // SaTr: trust region of one trial in beta = 2 sqrt(W) (Appendix B.1,
 // eqs. tr_sa, analysis_grad, analysis_hess)
 // ---------------------------------------------------------------------------
-template <int NC>
+template <int NC, bool PM>
 struct SaTrItem {
+    Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_SATR;
     static constexpr int NP = Tri<NC>::N;
     int64_t m;
@@ -508,15 +549,16 @@ struct SaTrItem {
 
     __device__ __forceinline__ bool step(const Ctx<NC> &c)
     {
+        const Props pp = mix_props<NC, PM>(c.pr, m);
         const FlashArgs &a = c.a;
         double W[NC];
 #pragma unroll
         for (int i = 0; i < NC; ++i) W[i] = exp(lw[i]);
         fl += NC;
         Phase<NC> o;
-        phase_eval<NC>(o, e, c.pr.K, W, fl);
+        phase_eval<NC>(o, e, pp.K, W, fl);
         double F[NP], Hs[NP], dinv[NC];
-        phase_derivs<NC>(F, o, e, c.pr.K, fl);
+        phase_derivs<NC>(F, o, e, pp.K, fl);
         double grad[NC], g[NC], tm = 1.0, sw = 0.0, gmax = 0.0;
 #pragma unroll
         for (int i = 0; i < NC; ++i) {
@@ -602,8 +644,9 @@ struct SaTrItem {
 // ---------------------------------------------------------------------------
 // SaFin: label decision and K re-estimate (Sec. 2.2.1, last paragraph)
 // ---------------------------------------------------------------------------
-template <int NC>
+template <int NC, bool PM>
 struct SaFinItem {
+    Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_SAFIN;
     int64_t m;
 
@@ -638,7 +681,7 @@ struct SaFinItem {
         r.theta = 0.5;
         r.status = status;
         r.fl = fl + NC;
-        push(c.L, L_SPLIT, (uint32_t)m);
+        ob.put(L_SPLIT, (uint32_t)m);
         return true;
     }
 };
@@ -646,8 +689,9 @@ struct SaFinItem {
 // ---------------------------------------------------------------------------
 // SpSs: successive substitution of the split (Sec. 2.2.2)
 // ---------------------------------------------------------------------------
-template <int NC>
+template <int NC, bool PM>
 struct SpSsItem {
+    Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_SPLIT;
     int64_t m;
     double z[NC], lk[NC], prev[NC];
@@ -688,6 +732,7 @@ struct SpSsItem {
 
     __device__ __forceinline__ bool step(const Ctx<NC> &c)
     {
+        const Props pp = mix_props<NC, PM>(c.pr, m);
         const FlashArgs &a = c.a;
         double x[NC], y[NC];
         if (!xy_from_lnk<NC>(x, y, lk, z, theta, fl)) {
@@ -695,11 +740,11 @@ struct SpSsItem {
             return true;
         }
         Phase<NC> o;
-        phase_eval<NC>(o, e, c.pr.K, x, fl);
+        phase_eval<NC>(o, e, pp.K, x, fl);
         double r0[NC];
 #pragma unroll
         for (int i = 0; i < NC; ++i) r0[i] = o.lnphi[i];
-        phase_eval<NC>(o, e, c.pr.K, y, fl);
+        phase_eval<NC>(o, e, pp.K, y, fl);
         // G per unit feed (eq. gibbs) where an acceleration check needs it
         const bool dem_next = a.dem_every > 0 && ss + 1 >= 2 && ((ss + 1) % a.dem_every) == 0;
         double G = 0.0;
@@ -747,7 +792,7 @@ struct SpSsItem {
         r.it[5] = (int16_t)ss;
         r.fl = fl;
         r.status = status | (conv ? 0u : kStSplitTr);
-        push(c.L, L_NT, (uint32_t)m);
+        ob.put(L_NT, (uint32_t)m);
         return true;
     }
 };
@@ -756,8 +801,9 @@ struct SpSsItem {
 // SpNt: trust region on G over n^V (Appendix B.2, eqs. newton_splitter,
 // split_grad, split_hess), Newton refinement, outputs
 // ---------------------------------------------------------------------------
-template <int NC>
+template <int NC, bool PM>
 struct SpNtItem {
+    Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_NT;
     static constexpr int NP = Tri<NC>::N;
     int64_t m;
@@ -855,6 +901,7 @@ struct SpNtItem {
 
     __device__ __forceinline__ bool step(const Ctx<NC> &c)
     {
+        const Props pp = mix_props<NC, PM>(c.pr, m);
         const FlashArgs &a = c.a;
         double w0[NC], w1[NC], bvap;
         xy_from_nv(w0, w1, bvap);
@@ -866,8 +913,8 @@ struct SpNtItem {
         fl += 4 * NC;
         double F[NP], Hs[NP], dinv[NC];
         Phase<NC> o;
-        phase_eval<NC>(o, e, c.pr.K, w0, fl);
-        phase_derivs<NC>(F, o, e, c.pr.K, fl);
+        phase_eval<NC>(o, e, pp.K, w0, fl);
+        phase_derivs<NC>(F, o, e, pp.K, fl);
 #pragma unroll
         for (int i = 0; i < NC; ++i)
 #pragma unroll
@@ -877,8 +924,8 @@ struct SpNtItem {
         const double Z0 = o.Z;
 #pragma unroll
         for (int i = 0; i < NC; ++i) r0[i] = o.lnphi[i];
-        phase_eval<NC>(o, e, c.pr.K, w1, fl);
-        phase_derivs<NC>(F, o, e, c.pr.K, fl);
+        phase_eval<NC>(o, e, pp.K, w1, fl);
+        phase_derivs<NC>(F, o, e, pp.K, fl);
         const double th = bvap;
         // gradient of G over n^V (eq. split_grad) and G itself (eq. gibbs)
         double gt[NC], gs[NC], G = 0.0, gmax = 0.0;

@@ -83,8 +83,8 @@ struct Phase {
 // Minimum-Gibbs root of Z^3 - Z^2 + (A - B - B^2) Z - AB = 0 (eq. cubic_Z).
 // Halley's iteration (eq. halley) from the liquid-like start Z = B, kept
 // inside the sign-change bracket [B, 1+B] (f(B) = -2B^2 < 0, f(1+B) = A > 0),
-// stopping at |Z_new/Z - 1| < 1e-8 after a Halley step or at an exact zero of
-// f; deflation to a quadratic for the other
+// stopping when a Halley step is below 1e-8 Z or at an exact zero of f;
+// deflation to a quadratic for the other
 // roots; physical roots are those above B; each kept root gets one Newton
 // correction on the full cubic; between the smallest (liquid) and largest
 // (vapour) root the one with the lower reduced residual Gibbs energy
@@ -102,14 +102,19 @@ __device__ __forceinline__ void cubic_root(double A, double B, double &Zout, dou
         const double fp = (3.0 * Z - 2.0) * Z + r1;
         const double fpp = 6.0 * Z - 2.0;
         if (f < 0.0) lo = Z; else hi = Z;
-        double Zn = Z - (2.0 * f * fp) / (2.0 * fp * fp - f * fpp);
-        const bool halley = (Zn > lo && Zn < hi);
-        if (!halley) Zn = 0.5 * (lo + hi);
-        const double dz = Zn - Z;
-        Z = Zn;
-        // the paper's test |Z_new/Z - 1| < 1e-8, on Halley steps only (a small
-        // bisection step says nothing about the distance to the root)
-        if (halley && fabs(dz) < 1e-8 * Z) break;
+        const double Zn = Z - (2.0 * f * fp) / (2.0 * fp * fp - f * fpp);
+        // the paper's test |Z_new/Z - 1| < 1e-8 on the Halley step.  It is
+        // taken before the bracket test: at the root to rounding the step is
+        // zero and lands on the end point just moved to Z, which must count
+        // as converged, not as a step leaving the bracket (bisecting from
+        // there walks back to the root one bit per iteration).
+        if (fabs(Zn - Z) < 1e-8 * Z) {
+            Z = fmin(fmax(Zn, lo), hi);
+            break;
+        }
+        // a small bisection step says nothing about the distance to the root,
+        // so only Halley steps are tested
+        Z = (Zn > lo && Zn < hi) ? Zn : 0.5 * (lo + hi);
         if (!(hi - lo > 0.0)) break;
     }
     fl += Cost<1>::halley * (uint32_t)(it + 1);
@@ -284,12 +289,15 @@ __device__ __forceinline__ bool rr_solve(const double (&z)[NC], const double (&K
         const double da = t - al, db = ar - t;
         const double h = da * db * f;
         const double hp = (db - da) * f + da * db * fp;
-        double tn = t - h / hp;
-        bool newton = true;
-        if (!(tn > lo && tn < hi)) { tn = 0.5 * (lo + hi); newton = false; }
-        const double step = tn - t;
-        t = tn;
-        if (newton && fabs(step) < 1e-8) break;
+        const double tn = t - h / hp;
+        // converged Newton step (tested before the bracket test, for the
+        // same reason as in cubic_root: at the root the step is zero and
+        // lands on the end point just moved to t)
+        if (fabs(tn - t) < 1e-8) {
+            t = fmin(fmax(tn, lo), hi);
+            break;
+        }
+        t = (tn > lo && tn < hi) ? tn : 0.5 * (lo + hi);
         if (!(hi - lo > 0.0)) break;
     }
     fl += Cost<NC>::rr_iter * (uint32_t)(it + 1);

@@ -105,3 +105,59 @@ def cotangents(seed: int, n: int, nc: int):
     """Upstream cotangents on (beta, x, y) ~ N(0, 1)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.standard_normal(n), rng.standard_normal((n, nc)), rng.standard_normal((n, nc))
+
+
+@dataclass
+class RaggedWorkload:
+    """Mixtures with their own component counts and component sets, packed:
+    mixture m's rows are off[m]:off[m+1] of z, Tc, Pc, omega; its k block
+    (nc_of[m]^2 values, row-major) starts at koff[m]."""
+    name: str
+    n: int
+    nc_of: np.ndarray   # (n,) int32
+    off: np.ndarray     # (n+1,) int64
+    koff: np.ndarray    # (n,) int64
+    z: np.ndarray
+    T: np.ndarray
+    P: np.ndarray
+    Tc: np.ndarray
+    Pc: np.ndarray
+    omega: np.ndarray
+    kij: np.ndarray
+
+    def group(self, nc: int):
+        """(indices, per-mixture-set Workload) of the mixtures with this nc."""
+        idx = np.where(self.nc_of == nc)[0]
+        rows = (self.off[idx][:, None] + np.arange(nc)[None, :])
+        kb = (self.koff[idx][:, None] + np.arange(nc * nc)[None, :])
+        w = Workload(f"{self.name}_nc{nc}", len(idx), nc, self.z[rows], self.T[idx],
+                     self.P[idx], self.Tc[rows], self.Pc[rows], self.omega[rows],
+                     self.kij[kb].reshape(len(idx), nc, nc), True)
+        return idx, w
+
+
+def ragged_workload(name: str, seed: int, n: int, nc_set=(2, 4, 6, 8, 12, 16, 20),
+                    alpha: float = 0.5, T_range=(200.0, 600.0),
+                    P_range=(1.0e5, 2.0e7)) -> RaggedWorkload:
+    """nc ~ U(nc_set) per mixture, then per mixture (in index order) its
+    component set (as in step 1 of the module docstring) and its feed
+    z ~ Dirichlet(alpha * 1); then T and P for all mixtures."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nc_of = rng.choice(np.asarray(nc_set, dtype=np.int32), size=n).astype(np.int32)
+    off = np.zeros(n + 1, dtype=np.int64)
+    off[1:] = np.cumsum(nc_of)
+    ksz = nc_of.astype(np.int64) ** 2
+    koff = np.zeros(n, dtype=np.int64)
+    koff[1:] = np.cumsum(ksz)[:-1]
+    tot, ktot = int(off[-1]), int(ksz.sum())
+    z = np.empty(tot); Tc = np.empty(tot); Pc = np.empty(tot); om = np.empty(tot)
+    kij = np.empty(ktot)
+    for m in range(n):
+        nc = int(nc_of[m])
+        a, b = off[m], off[m + 1]
+        Tc[a:b], Pc[a:b], om[a:b], k = _component_set(rng, nc)
+        kij[koff[m]:koff[m] + nc * nc] = k.ravel()
+        z[a:b] = rng.dirichlet(np.full(nc, alpha))
+    T = rng.uniform(T_range[0], T_range[1], n)
+    P = rng.uniform(P_range[0], P_range[1], n)
+    return RaggedWorkload(name, n, nc_of, off, koff, z, T, P, Tc, Pc, om, kij)

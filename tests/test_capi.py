@@ -53,3 +53,31 @@ def test_rejects_malformed_calls_without_gpu():
     assert L.ptflash_flash(C.byref(p0), C.byref(o), C.byref(r), None, 0, None) == 0
     assert L.ptflash_workspace_bytes(C.byref(p), C.byref(o)) >= 8
     assert L.ptflash_strerror(3) == b"workspace too small"
+    # one component set per mixture is accepted; other values are not
+    pm = _capi.Problem(n=5, nc=3, props_per_mixture=2, z=8, T=8, P=8, Tc=8, Pc=8, omega=8,
+                       kij=8)
+    assert L.ptflash_flash(C.byref(pm), C.byref(o), C.byref(r), None, 0, None) == 1
+    pm.props_per_mixture = 1
+    assert L.ptflash_flash(C.byref(pm), C.byref(o), C.byref(r), None, 0, None) == 3
+
+
+def test_ragged_entry_rejects_malformed_calls_without_gpu():
+    L = _capi.lib()
+    o = _capi.default_options()
+    r = _capi.Result(label=8, beta=8, x=8, y=8)
+    p = _capi.RaggedProblem(n=0)
+    assert L.ptflash_flash_ragged(C.byref(p), C.byref(o), C.byref(r), None, 0, None) == 0
+    p = _capi.RaggedProblem(n=-1)
+    assert L.ptflash_flash_ragged(C.byref(p), C.byref(o), C.byref(r), None, 0, None) == 1
+    full = dict(n=10, nc_of=8, off=8, koff=8, z=8, T=8, P=8, Tc=8, Pc=8, omega=8, kij=8)
+    p = _capi.RaggedProblem(**{**full, "koff": None})
+    assert L.ptflash_flash_ragged(C.byref(p), C.byref(o), C.byref(r), None, 0, None) == 1
+    p = _capi.RaggedProblem(**full)
+    ko = _capi.default_options(keep_factor=1)
+    assert L.ptflash_flash_ragged(C.byref(p), C.byref(ko), C.byref(r), None, 0, None) == 1
+    assert L.ptflash_flash_ragged(C.byref(p), C.byref(o), C.byref(r), None, 0, None) == 3
+    need = L.ptflash_ragged_workspace_bytes(C.byref(p), C.byref(o))
+    assert need > 10 * 4
+    # the workspace does not grow with nc beyond what one chunk needs
+    big = _capi.RaggedProblem(**{**full, "n": 1 << 22})
+    assert L.ptflash_ragged_workspace_bytes(C.byref(big), C.byref(o)) < 64 * 2 ** 30

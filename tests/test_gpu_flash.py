@@ -45,7 +45,7 @@ def test_nc3_full_parity():
     print(f"case nc3 n={w.n}", flush=True)
     g = _run(w)
     o = _oracle(w)
-    rep = compare(g, o)
+    rep = compare(g, o, w=w)
     _report("nc3", rep)
     inv = invariants(w, g)
     _report("nc3 invariants", inv)
@@ -65,7 +65,7 @@ def test_nc8_full_size_sampled_parity():
     rng = np.random.Generator(np.random.PCG64(7))
     idx = np.sort(rng.choice(w.n, 3000, replace=False))
     o = _oracle(w, idx)
-    rep = compare(g, o, idx)
+    rep = compare(g, o, idx, w=w)
     _report("nc8 sample", rep)
     _assert_parity(rep)
 
@@ -112,7 +112,7 @@ def test_ragged_sizes(n):
     w = workloads.nc8_workload(n=n, seed=99)
     print(f"case ragged n={n}", flush=True)
     g = _run(w)
-    rep = compare(g, _oracle(w))
+    rep = compare(g, _oracle(w), w=w)
     _report(f"ragged {n}", rep)
     _assert_parity(rep, path_agree=0.95)
 
@@ -124,15 +124,33 @@ def test_empty_batch():
     assert r.label.numel() == 0
 
 
-@pytest.mark.parametrize("nc", [2, 12])
+@pytest.mark.parametrize("nc", [2, 12, 16, 20])
 def test_extreme_component_counts(nc):
     w = workloads.uniform_workload(f"nc{nc}", 1000 + nc, 3000, nc, 0.7, (200.0, 600.0),
                                    (1e5, 2e7))
     print(f"case nc={nc}", flush=True)
     g = _run(w)
-    rep = compare(g, _oracle(w))
+    rep = compare(g, _oracle(w), w=w)
     _report(f"nc{nc}", rep)
     _assert_parity(rep, path_agree=0.97)
+
+
+@pytest.mark.parametrize("nc", [4, 8, 20])
+def test_per_mixture_component_sets(nc):
+    # one seeded component set per mixture (props_per_mixture = 1)
+    w = workloads.uniform_workload(f"pm{nc}", 2000 + nc, 3000, nc, 0.5, (200.0, 600.0),
+                                   (1e5, 2e7), per_mixture=True)
+    print(f"case per-mixture sets nc={nc}", flush=True)
+    g = _run(w)
+    inv = invariants(w, g)
+    _report(f"pm{nc} invariants", inv)
+    assert inv["mass_balance"] < 1e-13 and inv["single_ok"] and inv["labels_valid"]
+    rep = compare(g, _oracle(w), w=w)
+    _report(f"pm{nc}", rep)
+    _assert_parity(rep, path_agree=0.97)
+    gp = _run(w, form=_capi.FORM_PLAIN)
+    for k in ("label", "beta", "x", "y", "iters", "status"):
+        assert np.array_equal(g[k], gp[k], equal_nan=True), k
 
 
 def test_invalid_inputs_flagged():
