@@ -98,6 +98,29 @@ __device__ __forceinline__ void stage_slot(const Lists &L, int list, int l, uint
     fill += tot;
 }
 
+// Appends the entries of one outbox slot of every active lane whose slot
+// names `list` directly to the global list (one atomic per wavefront; the
+// plain form, where lanes beyond the active count have returned).
+__device__ __forceinline__ void append_slot(const Lists &L, int list, int l, uint32_t i, int n,
+                                            int lane)
+{
+    const bool mine = (l == list);
+    const unsigned long long m1 = __ballot(mine);
+    if (m1 == 0ull) return;
+    const unsigned long long m2 = __ballot(mine && n == 2);
+    const int tot = __popcll(m1) + __popcll(m2);
+    const int leader = __ffsll((unsigned long long)__ballot(1)) - 1;   // lowest active lane
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(&L.count[list], (unsigned long long)tot);
+    base = bcast64(base, leader);
+    if (mine) {
+        const unsigned long long b = lanes_below(lane);
+        const unsigned long long r = base + (unsigned long long)(__popcll(m1 & b) + __popcll(m2 & b));
+        L.ids[list][r] = i;
+        if (n == 2) L.ids[list][r + 1] = i + 1u;
+    }
+}
+
 // Persistent stage: one item per lane; lanes whose item finished take the
 // next ids of the wavefront's claimed chunk (one atomic per kChunk ids), and
 // the list entries the steps produce are staged per wavefront in LDS and
@@ -105,7 +128,7 @@ __device__ __forceinline__ void stage_slot(const Lists &L, int list, int l, uint
 // within its stage's iteration caps (and kStepGuard steps), so every
 // wavefront reaches the exit, where it appends what it still holds.
 template <class Item, int NC>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Item::WAVES)))
 stage_persistent(Ctx<NC> c, const double *__restrict__ Tc, const double *__restrict__ Pc,
                  const double *__restrict__ om, const double *__restrict__ K,
                  unsigned long long *__restrict__ take)
@@ -193,7 +216,12 @@ stage_plain_step(Ctx<NC> c, const double *__restrict__ Tc, const double *__restr
     Item it = states[k];
     it.ob.clear();
     const bool done = it.step(c);
-    push_outbox(c.L, it.ob);
+    const int lane = (int)__lane_id();
+#pragma unroll
+    for (int l = 0; l < L_COUNT; ++l) {
+        append_slot(c.L, l, it.ob.l0, it.ob.i0, it.ob.n0, lane);
+        append_slot(c.L, l, it.ob.l1, it.ob.i1, 1, lane);
+    }
     if (!done) {
         states[k] = it;
         next[atomicAdd(nnext, 1ull)] = k;
@@ -377,14 +405,17 @@ int device_cus()
 
 // Workspace: counters | per-mixture records | stage lists | (plain form:)
 // item states and two active lists.
-constexpr int kNumCounters = 16;   // L_COUNT list counts, 6 take counters, 2 plain
+constexpr int kNumStages = 7;
+constexpr int kNumCounters = 16;   // L_COUNT list counts, kNumStages take counters, 2 plain
 constexpr int kTake0 = L_COUNT;
-constexpr int kPlain0 = L_COUNT + 6;
+constexpr int kPlain0 = L_COUNT + kNumStages;
+static_assert(kPlain0 + 2 <= kNumCounters, "counter block too small");
 
 template <int NC>
 size_t plain_state_bytes()
 {
-    size_t m = sizeof(PreItem<NC, false>);
+    size_t m = sizeof(FeedItem<NC, false>);
+    m = m > sizeof(PreSsItem<NC, false>) ? m : sizeof(PreSsItem<NC, false>);
     m = m > sizeof(SaSsItem<NC, false>) ? m : sizeof(SaSsItem<NC, false>);
     m = m > sizeof(SaTrItem<NC, false>) ? m : sizeof(SaTrItem<NC, false>);
     m = m > sizeof(SaFinItem<NC, false>) ? m : sizeof(SaFinItem<NC, false>);
@@ -425,7 +456,7 @@ void setup_ctx(Ctx<NC> &c, const FlashArgs &a, int64_t n, void *ws, char **tail)
     c.rec = cv.take<MixRec<NC>>((size_t)n * sizeof(MixRec<NC>));
     c.L.ids[L_SA] = cv.take<uint32_t>(2 * (size_t)n * 4);
     c.L.ids[L_SATR] = cv.take<uint32_t>(2 * (size_t)n * 4);
-    cv.take<uint32_t>(2 * (size_t)n * 4);   // spare (keeps the layout aligned to the size formula)
+    c.L.ids[L_PRE] = cv.take<uint32_t>(2 * (size_t)n * 4);
     c.L.ids[L_SAFIN] = cv.take<uint32_t>((size_t)n * 4);
     c.L.ids[L_SPLIT] = cv.take<uint32_t>((size_t)n * 4);
     c.L.ids[L_NT] = cv.take<uint32_t>((size_t)n * 4);
@@ -466,12 +497,13 @@ int launch_persistent(const FlashArgs &a, const ptflash_problem *p, const ptflas
     setup_ctx<NC>(c, a, p->n, ws, &tail);
     hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, c.L.count, kNumCounters);
     int rc;
-    if ((rc = run_persistent_stage<PreItem<NC, PM>, NC>(c, p, o, kTake0 + 0, s))) return rc;
-    if ((rc = run_persistent_stage<SaSsItem<NC, PM>, NC>(c, p, o, kTake0 + 1, s))) return rc;
-    if ((rc = run_persistent_stage<SaTrItem<NC, PM>, NC>(c, p, o, kTake0 + 2, s))) return rc;
-    if ((rc = run_persistent_stage<SaFinItem<NC, PM>, NC>(c, p, o, kTake0 + 3, s))) return rc;
-    if ((rc = run_persistent_stage<SpSsItem<NC, PM>, NC>(c, p, o, kTake0 + 4, s))) return rc;
-    if ((rc = run_persistent_stage<SpNtItem<NC, PM>, NC>(c, p, o, kTake0 + 5, s))) return rc;
+    if ((rc = run_persistent_stage<FeedItem<NC, PM>, NC>(c, p, o, kTake0 + 0, s))) return rc;
+    if ((rc = run_persistent_stage<PreSsItem<NC, PM>, NC>(c, p, o, kTake0 + 1, s))) return rc;
+    if ((rc = run_persistent_stage<SaSsItem<NC, PM>, NC>(c, p, o, kTake0 + 2, s))) return rc;
+    if ((rc = run_persistent_stage<SaTrItem<NC, PM>, NC>(c, p, o, kTake0 + 3, s))) return rc;
+    if ((rc = run_persistent_stage<SaFinItem<NC, PM>, NC>(c, p, o, kTake0 + 4, s))) return rc;
+    if ((rc = run_persistent_stage<SpSsItem<NC, PM>, NC>(c, p, o, kTake0 + 5, s))) return rc;
+    if ((rc = run_persistent_stage<SpNtItem<NC, PM>, NC>(c, p, o, kTake0 + 6, s))) return rc;
     return PTFLASH_OK;
 }
 
@@ -525,7 +557,8 @@ int launch_plain(const FlashArgs &a, const ptflash_problem *p, void *ws, hipStre
     setup_ctx<NC>(c, a, p->n, ws, &tail);
     hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, c.L.count, kNumCounters);
     int rc;
-    if ((rc = run_plain_stage<PreItem<NC, PM>, NC>(c, p, tail, s))) return rc;
+    if ((rc = run_plain_stage<FeedItem<NC, PM>, NC>(c, p, tail, s))) return rc;
+    if ((rc = run_plain_stage<PreSsItem<NC, PM>, NC>(c, p, tail, s))) return rc;
     if ((rc = run_plain_stage<SaSsItem<NC, PM>, NC>(c, p, tail, s))) return rc;
     if ((rc = run_plain_stage<SaTrItem<NC, PM>, NC>(c, p, tail, s))) return rc;
     if ((rc = run_plain_stage<SaFinItem<NC, PM>, NC>(c, p, tail, s))) return rc;

@@ -4,8 +4,10 @@
 // call sites, so lanes of a wavefront evaluate the equation of state together).
 //
 // Stages (Sec. 2.2.3 strategy; Sec. 3 vectorisation with a barrier per stage):
-//   Pre    one per mixture: feed evaluation d = ln z + ln phi(z), Wilson K,
-//          three phase-split substitutions, triage into cases 1/2/3
+//   Feed   one per mixture: feed evaluation d = ln z + ln phi(z), Wilson K,
+//          the first Rachford-Rice decision (case 1 goes straight on)
+//   PreSs  one per remaining mixture: the initial phase-split substitutions,
+//          triage into cases 1/2/3
 //   SaSs   one per stability trial (V or L): successive substitution with
 //          dominant-eigenvalue acceleration (Sec. 2.2.1)
 //   SaTr   one per trial that needed more: trust region in beta = 2 sqrt(W)
@@ -74,7 +76,7 @@ struct MixRec {
 
 
 // Work lists: ids (mixture m, or trial 2m + t) and their counts.
-enum ListId : int { L_SA = 0, L_SATR = 1, L_SAFIN = 2, L_SPLIT = 3, L_NT = 4, L_COUNT = 5 };
+enum ListId : int { L_SA = 0, L_SATR = 1, L_SAFIN = 2, L_SPLIT = 3, L_NT = 4, L_PRE = 5, L_COUNT = 6 };
 
 struct Lists {
     uint32_t *ids[L_COUNT];
@@ -110,12 +112,6 @@ __device__ __forceinline__ Props mix_props(const Props &pr, int64_t m)
     }
 }
 
-__device__ __forceinline__ void push(const Lists &L, int list, uint32_t id)
-{
-    const unsigned long long k = atomicAdd(&L.count[list], 1ull);
-    L.ids[list][k] = id;
-}
-
 // What one step of an item hands to later stages: at most two list entries,
 // the first of which may be a pair of consecutive ids (the two stability
 // trials 2m, 2m + 1 of a mixture).  The stage kernel appends them to the
@@ -142,16 +138,6 @@ struct Outbox {
         n0 = 2;
     }
 };
-
-// Appends an outbox directly (one atomic per entry; the plain form).
-__device__ __forceinline__ void push_outbox(const Lists &L, const Outbox &ob)
-{
-    if (ob.l0 >= 0) {
-        push(L, ob.l0, ob.i0);
-        if (ob.n0 == 2) push(L, ob.l0, ob.i0 + 1u);
-    }
-    if (ob.l1 >= 0) push(L, ob.l1, ob.i1);
-}
 
 // ---------------------------------------------------------------------------
 // Shared helpers
@@ -246,20 +232,52 @@ __device__ __forceinline__ double ss_update(double (&v)[NC], double (&prev)[NC],
 }
 
 // ---------------------------------------------------------------------------
-// Pre: feed, Wilson, three substitutions, triage (Sec. 2.2.3)
+// Feed: input checks, EOS constants, feed evaluation, Wilson K and the first
+// Rachford-Rice decision of the initial substitutions (Sec. 2.2.1, 2.2.3)
 // ---------------------------------------------------------------------------
 template <int NC, bool PM>
-struct PreItem {
+__device__ __forceinline__ void wilson_lnk(double (&lk)[NC], const Props &pr, double T, double P)
+{
+#pragma unroll
+    for (int i = 0; i < NC; ++i)
+        lk[i] = log(pr.Pc[i] / P) + kWilson * (1.0 + pr.om[i]) * (1.0 - pr.Tc[i] / T);
+}
+
+// The record fields every later stage reads, and the routing of a mixture
+// that leaves the initial substitutions: to the split (case 3) or to the
+// stability analysis (cases 1, 2).
+template <int NC>
+__device__ __forceinline__ void route_mixture(MixRec<NC> &r, Outbox &ob, int64_t m, bool to_split,
+                                              uint32_t status, uint32_t fl, int npre,
+                                              const double (&lk)[NC], double theta)
+{
+#pragma unroll
+    for (int i = 0; i < NC; ++i) r.lk[i] = lk[i];
+    r.theta = theta;
+    r.status = status;
+    r.fl = fl;
+    r.tfl[0] = r.tfl[1] = 0;
+    r.tst[0] = r.tst[1] = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r.it[k] = 0;
+    r.it[0] = (int16_t)npre;
+    if (to_split) {
+        ob.put(L_SPLIT, (uint32_t)m);
+    } else {
+        ob.put_pair(L_SA, (uint32_t)(2 * m));
+        ob.put(L_SAFIN, (uint32_t)m);
+    }
+}
+
+template <int NC, bool PM>
+struct FeedItem {
+    static constexpr int WAVES = 1;   // minimum wavefronts per SIMD
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = -1;   // input: mixtures 0..n-1
     int64_t m;
     double T, P;
-    double z[NC], d[NC], lk[NC];
+    double z[NC];
     Eos<NC> e;
-    double theta;
-    int phase;   // 0: feed evaluation pending; k >= 1: k-th substitution
-    int steps;
-    uint32_t fl;
 
     __device__ __forceinline__ bool begin(const Ctx<NC> &c, uint32_t id)
     {
@@ -268,10 +286,6 @@ struct PreItem {
         const Props pp = mix_props<NC, PM>(c.pr, m);
         T = a.T[m];
         P = a.P[m];
-        fl = 0;
-        steps = 0;
-        phase = 0;
-        theta = 0.5;
         bool ok = (T > 0.0) && (P > 0.0) && isfinite(T) && isfinite(P);
         double s = 0.0;
 #pragma unroll
@@ -300,60 +314,84 @@ struct PreItem {
         return true;
     }
 
-    // stores what the later stages need and routes the mixture
-    __device__ __forceinline__ void route(const Ctx<NC> &c, bool to_split, uint32_t status,
-                                          const double (&lkw)[NC])
+    __device__ __forceinline__ bool step(const Ctx<NC> &c)
     {
+        const Props pp = mix_props<NC, PM>(c.pr, m);
+        uint32_t fl = 0;
+        Phase<NC> o;
+        phase_eval<NC>(o, e, pp.K, z, fl);
         MixRec<NC> &r = c.rec[m];
+        double lkw[NC];
+        wilson_lnk<NC, PM>(lkw, pp, T, P);
 #pragma unroll
         for (int i = 0; i < NC; ++i) {
+            const double lz = log(z[i]);
             r.s[i] = e.s[i];
             r.b[i] = e.b[i];
-            r.lnz[i] = log(z[i]);
-            r.d[i] = d[i];
+            r.lnz[i] = lz;
+            r.d[i] = lz + o.lnphi[i];
             r.lkw[i] = lkw[i];
-            r.lk[i] = lk[i];
         }
-        fl += NC;
-        r.theta = theta;
-        r.status = status;
-        r.fl = fl;
-        r.tfl[0] = r.tfl[1] = 0;
-        r.tst[0] = r.tst[1] = 0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) r.it[k] = 0;
-        r.it[0] = (int16_t)(phase - 1 < 0 ? 0 : phase - 1);
-        if (to_split) {
-            ob.put(L_SPLIT, (uint32_t)m);
+        fl += 8 * NC;
+        // the first Rachford-Rice solve of the initial substitutions decides
+        // case 1 here; the other mixtures repeat it in PreSs
+        double x[NC], y[NC], theta = 0.5;
+        uint32_t frr = 0;
+        const bool in = xy_from_lnk<NC>(x, y, lkw, z, theta, frr) && theta > 0.0 && theta < 1.0;
+        if (!in) {
+            route_mixture<NC>(r, ob, m, false, kStSaRan, fl + frr, 0, lkw, theta);
         } else {
-            ob.put_pair(L_SA, (uint32_t)(2 * m));
-            ob.put(L_SAFIN, (uint32_t)m);
+            r.fl = fl;
+            ob.put(L_PRE, (uint32_t)m);
         }
+        return true;
     }
+};
 
-    __device__ __forceinline__ void wilson(double (&lk_out)[NC], const Props &pr) const
+// ---------------------------------------------------------------------------
+// PreSs: the initial phase-split substitutions and the triage (Sec. 2.2.3)
+// of the mixtures that Feed did not send to case 1
+// ---------------------------------------------------------------------------
+template <int NC, bool PM>
+struct PreSsItem {
+    static constexpr int WAVES = 1;   // minimum wavefronts per SIMD
+    Outbox ob;   // list entries produced by the current step
+    static constexpr int LIST = L_PRE;
+    int64_t m;
+    double z[NC], d[NC], lk[NC];
+    Eos<NC> e;
+    double theta;
+    int npre, steps;
+    uint32_t fl;
+
+    __device__ __forceinline__ bool begin(const Ctx<NC> &c, uint32_t id)
     {
+        m = id;
+        const MixRec<NC> &r = c.rec[m];
+        load_z<NC>(z, c.a, m);
 #pragma unroll
-        for (int i = 0; i < NC; ++i)
-            lk_out[i] = log(pr.Pc[i] / P) + kWilson * (1.0 + pr.om[i]) * (1.0 - pr.Tc[i] / T);
+        for (int i = 0; i < NC; ++i) {
+            e.s[i] = r.s[i];
+            e.b[i] = r.b[i];
+            d[i] = r.d[i];
+            lk[i] = r.lkw[i];
+        }
+        fl = r.fl;
+        theta = 0.5;
+        npre = 0;
+        steps = 0;
+        return true;
     }
 
     __device__ __forceinline__ bool step(const Ctx<NC> &c)
     {
         const Props pp = mix_props<NC, PM>(c.pr, m);
         const FlashArgs &a = c.a;
+        MixRec<NC> &r = c.rec[m];
         double w0[NC], w1[NC];
-        bool e1 = true;
-        if (phase == 0) {
-#pragma unroll
-            for (int i = 0; i < NC; ++i) w0[i] = z[i];
-            e1 = false;
-        } else if (!(xy_from_lnk<NC>(w0, w1, lk, z, theta, fl) && theta > 0.0 && theta < 1.0)) {
+        if (!(xy_from_lnk<NC>(w0, w1, lk, z, theta, fl) && theta > 0.0 && theta < 1.0)) {
             // case 1: the Rachford-Rice root left (0,1)
-            double lkw[NC];
-            wilson(lkw, pp);
-            fl += 5 * NC;
-            route(c, false, kStSaRan, lkw);
+            route_mixture<NC>(r, ob, m, false, kStSaRan, fl, npre, lk, theta);
             return true;
         }
         Phase<NC> o;
@@ -361,21 +399,12 @@ struct PreItem {
         double r0[NC];
 #pragma unroll
         for (int i = 0; i < NC; ++i) r0[i] = o.lnphi[i];
-        if (e1) phase_eval<NC>(o, e, pp.K, w1, fl);
-        if (phase == 0) {
-#pragma unroll
-            for (int i = 0; i < NC; ++i) d[i] = log(z[i]) + r0[i];
-            fl += 2 * NC;
-            wilson(lk, pp);
-            fl += 5 * NC;
-            phase = 1;
-            return false;
-        }
+        phase_eval<NC>(o, e, pp.K, w1, fl);
 #pragma unroll
         for (int i = 0; i < NC; ++i) lk[i] = r0[i] - o.lnphi[i];
         fl += NC;
-        ++phase;
-        if (phase - 1 < a.max_pre_ss && ++steps < kStepGuard) return false;
+        ++npre;
+        if (npre < a.max_pre_ss && ++steps < kStepGuard) return false;
         // triage (Sec. 2.2.3): tpd of the current liquid and vapour
         double tx = 0.0, ty = 0.0;
 #pragma unroll
@@ -385,15 +414,10 @@ struct PreItem {
         }
         const double dg = (1.0 - theta) * tx + theta * ty;
         fl += 8 * NC + 3;
-        double lkw[NC];
-        wilson(lkw, pp);
-        fl += 5 * NC;
-        if (tx < -a.eps_tm || ty < -a.eps_tm || dg < -a.eps_tm) {
-            theta = 0.5;
-            route(c, true, kStShortcut, lkw);
-        } else {
-            route(c, false, kStSaRan, lkw);
-        }
+        if (tx < -a.eps_tm || ty < -a.eps_tm || dg < -a.eps_tm)
+            route_mixture<NC>(r, ob, m, true, kStShortcut, fl, npre, lk, 0.5);
+        else
+            route_mixture<NC>(r, ob, m, false, kStSaRan, fl, npre, lk, theta);
         return true;
     }
 };
@@ -404,6 +428,7 @@ struct PreItem {
 // ---------------------------------------------------------------------------
 template <int NC, bool PM>
 struct SaSsItem {
+    static constexpr int WAVES = 1;   // minimum wavefronts per SIMD
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_SA;
     int64_t m;
@@ -503,6 +528,7 @@ struct SaSsItem {
 // ---------------------------------------------------------------------------
 template <int NC, bool PM>
 struct SaTrItem {
+    static constexpr int WAVES = 1;   // minimum wavefronts per SIMD
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_SATR;
     static constexpr int NP = Tri<NC>::N;
@@ -646,6 +672,7 @@ struct SaTrItem {
 // ---------------------------------------------------------------------------
 template <int NC, bool PM>
 struct SaFinItem {
+    static constexpr int WAVES = 1;   // minimum wavefronts per SIMD
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_SAFIN;
     int64_t m;
@@ -691,6 +718,7 @@ struct SaFinItem {
 // ---------------------------------------------------------------------------
 template <int NC, bool PM>
 struct SpSsItem {
+    static constexpr int WAVES = (NC <= 8 ? 2 : 1);   // minimum wavefronts per SIMD
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_SPLIT;
     int64_t m;
@@ -803,6 +831,7 @@ struct SpSsItem {
 // ---------------------------------------------------------------------------
 template <int NC, bool PM>
 struct SpNtItem {
+    static constexpr int WAVES = 1;   // minimum wavefronts per SIMD
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_NT;
     static constexpr int NP = Tri<NC>::N;

@@ -14,32 +14,58 @@ namespace ptf {
 
 constexpr int kBlock = 256;
 
-// Deterministic batch sum of the k contributions: one block per pair, each
-// thread sums a fixed strided subset in order, then a fixed tree in LDS.
-__global__ void __launch_bounds__(kBlock)
-reduce_pairs(const double *__restrict__ kpart, int64_t n, int nc, double *gk)
+// Deterministic batch sum of the k contributions in two passes.  Pass 1:
+// block (q, c) sums mixtures [c*kRedChunk, (c+1)*kRedChunk) of pair q (each
+// thread a fixed strided subset in order, then a fixed tree in LDS).  Pass
+// 2: one block per pair sums its chunk partials the same way.  The order of
+// every addition is fixed by n alone, so the result does not depend on
+// scheduling.
+constexpr int64_t kRedChunk = 16384;
+
+__device__ __forceinline__ double block_tree_sum(double v, double *red)
 {
-    __shared__ double red[kBlock];
-    const int q = blockIdx.x;
-    double acc = 0.0;
-    for (int64_t m = threadIdx.x; m < n; m += kBlock) acc += kpart[(int64_t)q * n + m];
-    red[threadIdx.x] = acc;
+    red[threadIdx.x] = v;
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
+    return red[0];
+}
+
+__global__ void __launch_bounds__(kBlock)
+reduce_pairs_chunks(const double *__restrict__ kpart, int64_t n, int64_t nchunk, double *part)
+{
+    __shared__ double red[kBlock];
+    const int64_t q = blockIdx.y, c = blockIdx.x;
+    const int64_t lo = c * kRedChunk, hi = lo + kRedChunk < n ? lo + kRedChunk : n;
+    double acc = 0.0;
+    for (int64_t m = lo + threadIdx.x; m < hi; m += kBlock) acc += kpart[q * n + m];
+    const double t = block_tree_sum(acc, red);
+    if (threadIdx.x == 0) part[q * nchunk + c] = t;
+}
+
+__global__ void __launch_bounds__(kBlock)
+reduce_pairs_final(const double *__restrict__ part, int64_t nchunk, int nc, double *gk)
+{
+    __shared__ double red[kBlock];
+    const int q = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t c = threadIdx.x; c < nchunk; c += kBlock) acc += part[(int64_t)q * nchunk + c];
+    const double t = block_tree_sum(acc, red);
     if (threadIdx.x == 0) {
         // pair index -> (i, j), i < j
         int i = 0, r = q;
         while (r >= nc - 1 - i) { r -= nc - 1 - i; ++i; }
         const int j = i + 1 + r;
-        gk[i * nc + j] = 0.5 * red[0];
-        gk[j * nc + i] = 0.5 * red[0];
+        gk[i * nc + j] = 0.5 * t;
+        gk[j * nc + i] = 0.5 * t;
         if (q == 0)
             for (int d = 0; d < nc; ++d) gk[d * nc + d] = 0.0;
     }
 }
+
+static int64_t red_chunks(int64_t n) { return (n + kRedChunk - 1) / kRedChunk; }
 
 static void fill_args(FlashArgs &a, const ptflash_problem *p, const ptflash_options *o,
                       const ptflash_result *r)
@@ -353,7 +379,9 @@ size_t ptflash_backward_workspace_bytes(const ptflash_problem *p, int32_t kij_re
 {
     if (!problem_ok(p)) return 0;
     const int64_t npair = (int64_t)p->nc * (p->nc - 1) / 2;
-    if (kij_reduce) return 256 + align256((size_t)npair * (size_t)p->n * sizeof(double));
+    if (kij_reduce)
+        return 256 + align256((size_t)npair * (size_t)p->n * sizeof(double)) +
+               align256((size_t)npair * (size_t)red_chunks(p->n) * sizeof(double));
     return 256;
 }
 
@@ -398,7 +426,11 @@ int ptflash_flash_backward(const ptflash_problem *p, const ptflash_options *o,
     if (rc) return rc;
     if (kij_reduce) {
         const int npair = p->nc * (p->nc - 1) / 2;
-        hipLaunchKernelGGL(reduce_pairs, dim3(npair), dim3(kBlock), 0, s, b.kpart, p->n, p->nc,
+        const int64_t nch = red_chunks(p->n);
+        double *part = b.kpart + align256((size_t)npair * (size_t)p->n * sizeof(double)) / 8;
+        hipLaunchKernelGGL(reduce_pairs_chunks, dim3((unsigned)nch, (unsigned)npair), dim3(kBlock),
+                           0, s, b.kpart, p->n, nch, part);
+        hipLaunchKernelGGL(reduce_pairs_final, dim3(npair), dim3(kBlock), 0, s, part, nch, p->nc,
                            g_kij);
         if (hipGetLastError() != hipSuccess) return PTFLASH_EHIP;
     }
