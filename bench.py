@@ -144,6 +144,10 @@ def main():
                      "traffic": traffic, "flops_per_flash": flops / w.n,
                      "kernel_ms": avg_ms},
         "two_phase_frac": float((g["label"] == 1).mean()),
+        # mean and max iteration counts per slot over the mixtures that ran it
+        "iters": {nm: [float(g["iters"][:, k][g["iters"][:, k] > 0].mean())
+                       if (g["iters"][:, k] > 0).any() else 0.0, int(g["iters"][:, k].max())]
+                  for k, nm in enumerate(_capi.IT_NAMES)},
         "status_counts": {k: int(((g["status"].astype(np.int64) & 0xffff) & v != 0).sum())
                           for k, v in _capi.ST.items()},
     }

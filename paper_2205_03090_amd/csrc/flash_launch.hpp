@@ -45,11 +45,24 @@ __device__ __forceinline__ uint32_t stage_id(const Ctx<NC> &c, int64_t k)
     return Item::LIST < 0 ? (uint32_t)k : c.L.ids[Item::LIST < 0 ? 0 : Item::LIST][k];
 }
 
-// Ids a wavefront claims from a stage's input with one atomic.
+// Ids a wavefront claims from a stage's input with one atomic (after its
+// static first share, three quarters of an even split of the input).
 constexpr int kChunk = 64;
-// Per-wavefront staging of list appends in LDS (entries per list).
-constexpr int kStage = 128;
+// Per-wavefront staging of list appends in LDS (entries per output list).
+constexpr int kStage = 512;
 constexpr int kWavesPerBlock = kBlock / 64;
+
+// Output lists of a stage: bit l of Item::OUT; slot_of<OUT>(l) is the list's
+// staging buffer.
+__host__ __device__ constexpr int popcount32(uint32_t v)
+{
+    return v == 0u ? 0 : (int)(v & 1u) + popcount32(v >> 1);
+}
+template <uint32_t OUT>
+__device__ constexpr int slot_of(int l)
+{
+    return popcount32(OUT & ((1u << l) - 1u));
+}
 
 // Wave-level helpers (called by all 64 lanes together).
 __device__ __forceinline__ unsigned long long lanes_below(int lane)
@@ -122,8 +135,9 @@ __device__ __forceinline__ void append_slot(const Lists &L, int list, int l, uin
 }
 
 // Persistent stage: one item per lane; lanes whose item finished take the
-// next ids of the wavefront's claimed chunk (one atomic per kChunk ids), and
-// the list entries the steps produce are staged per wavefront in LDS and
+// next ids of the wavefront's claimed range: first a static share, then
+// chunks of kChunk ids from the stage's counter (one atomic per chunk).  The
+// list entries the steps produce are staged per wavefront in LDS and
 // appended kStage at a time (one atomic per batch).  Every item finishes
 // within its stage's iteration caps (and kStepGuard steps), so every
 // wavefront reaches the exit, where it appends what it still holds.
@@ -133,15 +147,24 @@ stage_persistent(Ctx<NC> c, const double *__restrict__ Tc, const double *__restr
                  const double *__restrict__ om, const double *__restrict__ K,
                  unsigned long long *__restrict__ take)
 {
-    __shared__ uint32_t stage_buf[kWavesPerBlock][L_COUNT][kStage];
+    constexpr uint32_t OUT = Item::OUT;
+    constexpr int NOUT = popcount32(OUT) > 0 ? popcount32(OUT) : 1;
+    __shared__ uint32_t stage_buf[kWavesPerBlock][NOUT][kStage];
     c.pr = Props{Tc, Pc, om, K};
     const int64_t count = stage_count<Item, NC>(c);
     const int lane = (int)__lane_id();
     uint32_t(*buf)[kStage] = stage_buf[threadIdx.x / 64];
-    int fill[L_COUNT];
+    int fill[NOUT];
 #pragma unroll
-    for (int l = 0; l < L_COUNT; ++l) fill[l] = 0;
-    unsigned long long cb = 0, ce = 0;   // claimed, not yet taken: [cb, ce)
+    for (int l = 0; l < NOUT; ++l) fill[l] = 0;
+    // static first share of this wavefront: [wid*s0, (wid+1)*s0); the shared
+    // counter hands out ids from nw*s0 on
+    const unsigned long long nw = (unsigned long long)gridDim.x * (blockDim.x / 64);
+    const unsigned long long wid =
+        (unsigned long long)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    const unsigned long long s0 = (unsigned long long)(count > 0 ? count : 0) * 3ull / 4ull / nw;
+    const unsigned long long dyn0 = nw * s0;
+    unsigned long long cb = wid * s0, ce = cb + s0;   // claimed, not yet taken: [cb, ce)
     Item it;
     bool live = false, gone = false;
     for (;;) {
@@ -152,7 +175,7 @@ stage_persistent(Ctx<NC> c, const double *__restrict__ Tc, const double *__restr
             const unsigned long long avail = ce - cb;
             unsigned long long nb = 0;
             if (avail < (unsigned long long)r) {
-                if (lane == 0) nb = atomicAdd(take, (unsigned long long)kChunk);
+                if (lane == 0) nb = dyn0 + atomicAdd(take, (unsigned long long)kChunk);
                 nb = bcast64(nb, 0);
             }
             if (want) {
@@ -173,13 +196,20 @@ stage_persistent(Ctx<NC> c, const double *__restrict__ Tc, const double *__restr
         if (live) live = !it.step(c);
 #pragma unroll
         for (int l = 0; l < L_COUNT; ++l) {
-            stage_slot(c.L, l, it.ob.l0, it.ob.i0, it.ob.n0, buf[l], fill[l], lane);
-            stage_slot(c.L, l, it.ob.l1, it.ob.i1, 1, buf[l], fill[l], lane);
+            if ((OUT >> l) & 1u) {
+                const int q = slot_of<OUT>(l);
+                stage_slot(c.L, l, it.ob.l0, it.ob.i0, it.ob.n0, buf[q], fill[q], lane);
+                stage_slot(c.L, l, it.ob.l1, it.ob.i1, 1, buf[q], fill[q], lane);
+            }
         }
     }
 #pragma unroll
-    for (int l = 0; l < L_COUNT; ++l)
-        if (fill[l] > 0) flush_list(c.L, l, buf[l], fill[l], lane);
+    for (int l = 0; l < L_COUNT; ++l) {
+        if ((OUT >> l) & 1u) {
+            const int q = slot_of<OUT>(l);
+            if (fill[q] > 0) flush_list(c.L, l, buf[q], fill[q], lane);
+        }
+    }
 }
 
 // Plain form: begin every item of the stage and list the live ones ...

@@ -272,6 +272,7 @@ __device__ __forceinline__ void route_mixture(MixRec<NC> &r, Outbox &ob, int64_t
 template <int NC, bool PM>
 struct FeedItem {
     static constexpr int WAVES = 1;   // minimum wavefronts per SIMD
+    static constexpr uint32_t OUT = (1u << L_SA) | (1u << L_SAFIN) | (1u << L_PRE);   // lists the steps append to
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = -1;   // input: mixtures 0..n-1
     int64_t m;
@@ -355,6 +356,7 @@ struct FeedItem {
 template <int NC, bool PM>
 struct PreSsItem {
     static constexpr int WAVES = 1;   // minimum wavefronts per SIMD
+    static constexpr uint32_t OUT = (1u << L_SA) | (1u << L_SAFIN) | (1u << L_SPLIT);   // lists the steps append to
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_PRE;
     int64_t m;
@@ -429,6 +431,7 @@ struct PreSsItem {
 template <int NC, bool PM>
 struct SaSsItem {
     static constexpr int WAVES = 1;   // minimum wavefronts per SIMD
+    static constexpr uint32_t OUT = 1u << L_SATR;   // lists the steps append to
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_SA;
     int64_t m;
@@ -529,6 +532,7 @@ struct SaSsItem {
 template <int NC, bool PM>
 struct SaTrItem {
     static constexpr int WAVES = 1;   // minimum wavefronts per SIMD
+    static constexpr uint32_t OUT = 0u;   // lists the steps append to
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_SATR;
     static constexpr int NP = Tri<NC>::N;
@@ -673,6 +677,7 @@ struct SaTrItem {
 template <int NC, bool PM>
 struct SaFinItem {
     static constexpr int WAVES = 1;   // minimum wavefronts per SIMD
+    static constexpr uint32_t OUT = 1u << L_SPLIT;   // lists the steps append to
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_SAFIN;
     int64_t m;
@@ -719,6 +724,7 @@ struct SaFinItem {
 template <int NC, bool PM>
 struct SpSsItem {
     static constexpr int WAVES = (NC <= 8 ? 2 : 1);   // minimum wavefronts per SIMD
+    static constexpr uint32_t OUT = 1u << L_NT;   // lists the steps append to
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_SPLIT;
     int64_t m;
@@ -832,6 +838,7 @@ struct SpSsItem {
 template <int NC, bool PM>
 struct SpNtItem {
     static constexpr int WAVES = 1;   // minimum wavefronts per SIMD
+    static constexpr uint32_t OUT = 0u;   // lists the steps append to
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_NT;
     static constexpr int NP = Tri<NC>::N;
