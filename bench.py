@@ -189,7 +189,7 @@ def main():
                                                                        replace=False))
         o = oracle.flash(w.subset(idx), threads=min(16, os.cpu_count() or 1), want_min_tpd=1)
         rep = compare(gg, o, idx, verbose=False, w=w)
-        rec["parity"] = {k: rep[k] for k in ("n", "label_mismatch", "value_mismatch", "ref_unconverged",
+        rec["parity"] = {k: rep[k] for k in ("n", "label_mismatch", "value_mismatch", "ref_unconverged", "alt_split",
                                              "single_mismatch", "max_err", "ss_path_agree")}
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)

@@ -380,8 +380,11 @@ __device__ __forceinline__ double norm2(const double (&v)[NC])
 // when the unshifted Newton step is inside the region it is taken (eta = 0).
 // Otherwise eta is found in the bracket [max(0, -min H_ii),
 // ||g||/radius + max_i sum_j |H_ij|] (the upper end makes ||u|| <= radius):
-// a failed factorisation raises the lower end and moves eta to the geometric
-// mean of the bracket; a successful one takes a Newton step on Hebden's
+// when H is positive definite the search starts with the Newton update of
+// eta from 0 (using the factor of H already computed), otherwise at the lower
+// end (or 1e-3 of the upper end); a failed factorisation raises the lower
+// end and moves eta to the geometric mean of the bracket; a successful one
+// takes a Newton step on Hebden's
 // secular equation 1/||u(eta)|| = 1/radius, kept inside the bracket; ||u|| within
 // 10 % of the radius is accepted; at most 12 factorisations.  If no shift
 // succeeds, the Cauchy point (steepest descent minimising the model inside the
@@ -400,13 +403,25 @@ __device__ __forceinline__ double trust_step(double (&u)[NC], double &radius, bo
     for (int i = 0; i < NC; ++i) mg[i] = -g[i];
     eta0 = false;
     bool have = false;
+    double eta1 = -1.0;   // first shift from the eta = 0 factor, when positive definite
     if (cholesky<NC>(Lf, dinv, H, 0.0, fl)) {
         lower_solve<NC>(y, Lf, dinv, mg);
         upper_solve<NC>(u, Lf, dinv, y);
         fl += Cost<NC>::trisolve;
         const double nu = norm2<NC>(u);
         if (!(radius > 0.0)) radius = nu;
-        if (nu <= radius) { eta0 = true; have = true; }
+        if (nu <= radius) {
+            eta0 = true;
+            have = true;
+        } else {
+            // the Newton step leaves the region: the first Hebden update
+            // starts from eta = 0 with the factor in hand
+            double q[NC];
+            lower_solve<NC>(q, Lf, dinv, u);
+            const double nq = norm2<NC>(q);
+            eta1 = (nu / nq) * (nu / nq) * (nu - radius) / radius;
+            fl += NC * NC + 2 * NC + 6;
+        }
     } else if (!(radius > 0.0)) {
         radius = 1.0;
     }
@@ -423,6 +438,7 @@ __device__ __forceinline__ double trust_step(double (&u)[NC], double &radius, bo
         double elo = fmax(0.0, -hmin);
         double ehi = norm2<NC>(g) / radius + rowmax;
         double eta = elo > 0.0 ? elo : 1e-3 * ehi;
+        if (eta1 > 0.0 && eta1 < ehi) eta = eta1;
         for (int it = 0; it < 12; ++it) {
             if (!cholesky<NC>(Lf, dinv, H, eta, fl)) {
                 elo = eta;

@@ -208,3 +208,29 @@ def test_parity_validity_check_for_unconverged_references(orc, nc8):
     y[0] *= 1 + 1e-6
     y /= y.sum()
     assert split_residual_max(w, m, r["x"][m], y) > FUG_TOL
+
+
+def test_boundary_generator_straddles_the_oracle_boundary(orc):
+    # the bisected pressure lies where the oracle's label changes: 5 % below
+    # and above it the labels differ for most mixtures (the 2 % jitter and
+    # curved boundaries allow a few exceptions)
+    import hard_cases
+    w = hard_cases.boundary_workload(3, 40, nc=6, steps=25)
+    lo = workloads.Workload("lo", w.n, w.nc, w.z, w.T, w.P / 1.05, w.Tc, w.Pc, w.omega, w.kij)
+    hi = workloads.Workload("hi", w.n, w.nc, w.z, w.T, w.P * 1.05, w.Tc, w.Pc, w.omega, w.kij)
+    a = orc.flash(lo, threads=8)["label"]
+    b = orc.flash(hi, threads=8)["label"]
+    assert np.mean(a != b) > 0.8
+
+
+def test_parity_gibbs_of_a_split_matches_the_oracle_residual_routine(orc, nc8):
+    # the Gibbs energy used to rank alternative splits equals the one the
+    # oracle's split-residual routine returns for n^V = beta y
+    from parity import split_gibbs
+    w, r = nc8
+    two = np.where((r["label"] == 1) & (r["info"][:, 8] == 0))[0][:50]
+    for m in two:
+        z = w.z[m] / np.cumsum(w.z[m])[-1]
+        _, G = orc.split_residual(w.Tc, w.Pc, w.omega, w.kij, w.T[m], w.P[m], z,
+                                  r["beta"][m] * r["y"][m])
+        assert abs(split_gibbs(w, m, r["x"][m], r["y"][m], r["beta"][m]) - G) < 1e-12 * max(1, abs(G))
