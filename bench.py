@@ -6,7 +6,7 @@ throughput of the persistent form; `fwd_adjoint` times forward (keeping the
 factor) + implicit-function backward; `plain_form` times the plain
 one-launch-per-stage-iteration form on the same inputs.
 
-  python bench.py [--steps K] [--warmup W] [--workload nc8_1m|nc3_10k|nc10_1m]
+  python bench.py [--steps K] [--warmup W] [--workload nc8_1m|nc3_10k|nc10_1m|nc20_8m]
                   [--form persistent|plain] [--no-cpu-baseline] [--no-adjoint]
                   [--plain-steps N] [--check M]
 """
@@ -30,11 +30,14 @@ HBM_PEAK = 8.0e12
 
 
 def _kernel_sha() -> str:
+    """Hash of the kernel sources and the build script (its flags)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2205_03090_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
+    with open(os.path.join(ROOT, "paper_2205_03090_amd", "build.py"), "rb") as f:
+        h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -100,7 +103,7 @@ def main():
     from paper_2205_03090_amd import _capi, api, workloads
 
     makers = {"nc8_1m": workloads.nc8_workload, "nc3_10k": workloads.nc3_workload,
-              "nc10_1m": workloads.nc10_workload}
+              "nc10_1m": workloads.nc10_workload, "nc20_8m": workloads.nc20_workload}
     w = makers[args.workload]()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)

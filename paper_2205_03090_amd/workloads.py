@@ -101,6 +101,14 @@ def nc10_workload(n: int = 1_000_000, seed: int = SEEDS["nc10"]) -> Workload:
     return uniform_workload("nc10_1m", seed, n, 10, 0.5, (200.0, 600.0), (1.0e5, 2.0e7))
 
 
+def nc20_workload(n: int = 8_000_000, seed: int = SEEDS["nc20"]) -> Workload:
+    """Nc = 20, 8,000,000 mixtures, z ~ Dir(0.3 * 1), T ~ U[200,600] K,
+    P ~ U[1e5, 3e7] Pa, one shared component set (the uniform part of the
+    hard-case workload; the boundary-hugging part needs the oracle's labels
+    and is built by the tests)."""
+    return uniform_workload("nc20_8m", seed, n, 20, 0.3, (200.0, 600.0), (1.0e5, 3.0e7))
+
+
 def cotangents(seed: int, n: int, nc: int):
     """Upstream cotangents on (beta, x, y) ~ N(0, 1)."""
     rng = np.random.Generator(np.random.PCG64(seed))

@@ -188,8 +188,13 @@ def test_deterministic_across_runs_and_grids():
         assert np.array_equal(a[k], c[k], equal_nan=True), k
 
 
+def _nc20_shared(n):
+    return workloads.uniform_workload("p20", 920, n, 20, 0.3, (200.0, 600.0), (1e5, 3e7))
+
+
 @pytest.mark.parametrize("maker,n", [(workloads.nc3_workload, 10_000),
-                                     (workloads.nc8_workload, 50_000)])
+                                     (workloads.nc8_workload, 50_000),
+                                     (_nc20_shared, 3000)])
 def test_plain_form_bitwise_equal_to_persistent(maker, n):
     # the plain form (one launch per stage iteration, compaction, host count
     # read, stage barriers) runs the same per-mixture arithmetic
