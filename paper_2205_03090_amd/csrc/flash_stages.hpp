@@ -100,13 +100,26 @@ struct Ctx {
     Lists L;
 };
 
+// From this nc on, the k table of a shared set is read with vector loads
+// (all lanes at the same addresses, served by the L1 cache): its nc(nc-1)/2
+// values no longer fit the scalar registers, and the scalar-load form of the
+// largest kernels spilled hundreds of them.
+constexpr int kVectorKFromNc = 13;
+
 // Component set of mixture m: the shared set (wave-uniform loads), or, with
 // one set per mixture (PM), the mixture's own rows (nc values each, nc*nc k).
 template <int NC, bool PM>
 __device__ __forceinline__ Props mix_props(const Props &pr, int64_t m)
 {
     if constexpr (!PM) {
-        return pr;
+        if constexpr (NC >= kVectorKFromNc) {
+            // the empty asm makes the pointer a per-lane (VGPR) value
+            uintptr_t k = (uintptr_t)pr.K;
+            __asm__ volatile("" : "+v"(k));
+            return Props{pr.Tc, pr.Pc, pr.om, (const double *)k};
+        } else {
+            return pr;
+        }
     } else {
         return Props{pr.Tc + m * NC, pr.Pc + m * NC, pr.om + m * NC, pr.K + m * NC * NC};
     }
