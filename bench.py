@@ -41,17 +41,18 @@ def _kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def _traffic(workload: str, per_launch_flashes: int):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, or
-    None when they are missing or were taken on a different kernel source."""
+def _counters(workload: str) -> dict:
+    """Per-launch figures from the committed rocprofv3 counter summary of
+    this workload (HBM bytes, issued FP64 VALU flops), or {} when it is
+    missing or was taken on a different kernel source or build."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
-        return None
+        return {}
     with open(path) as f:
         t = json.load(f)
     if t.get("kernel_sha") != _kernel_sha():
-        return None
-    return t.get("bytes_per_launch")
+        return {}
+    return t
 
 
 def cpu_baseline(w, budget_s: float = 12.0):
@@ -81,6 +82,8 @@ def main():
     ap.add_argument("--check", type=int, default=2000, help="mixtures checked against the oracle")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--graph", action="store_true",
+                    help="also time replays of the persistent flash captured in a HIP graph")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -134,7 +137,8 @@ def main():
     flops = out.flops.to(torch.int64).sum().item()
     g = {k: getattr(out, k).cpu().numpy() for k in ("label", "iters", "status")}
     achieved = flops / (avg_ms * 1e-3)
-    traffic = _traffic(args.workload, w.n)
+    cnt = _counters(args.workload)
+    traffic = cnt.get("bytes_per_launch")
 
     rec = {
         "metric": METRIC, "value": value, "unit": "flashes/s", "n_gpus": 1,
@@ -147,6 +151,14 @@ def main():
                      "traffic": traffic, "flops_per_flash": flops / w.n,
                      "kernel_ms": avg_ms},
         "two_phase_frac": float((g["label"] == 1).mean()),
+        # the second roofline view: FP64 VALU flops the hardware issued per
+        # launch (rocprofv3 FP64 instruction counters, 64 lanes per wave
+        # instruction, FMA = 2; transcendental and division sequences
+        # included) over this run's launch time
+        "fp64_issued": ({"tflops": cnt["fp64_issued_flops_per_launch"] / (avg_ms * 1e-3) / 1e12,
+                         "frac": cnt["fp64_issued_flops_per_launch"] / (avg_ms * 1e-3)
+                         / FP64_VECTOR_PEAK}
+                        if "fp64_issued_flops_per_launch" in cnt else None),
         # mean and max iteration counts per slot over the mixtures that ran it
         "iters": {nm: [float(g["iters"][:, k][g["iters"][:, k] > 0].mean())
                        if (g["iters"][:, k] > 0).any() else 0.0, int(g["iters"][:, k].max())]
@@ -171,6 +183,24 @@ def main():
         rec["fwd_adjoint"] = {"value": w.n * args.steps / wall_a, "unit": "flashes/s",
                               "ms_per_step": wall_a * 1e3 / args.steps,
                               "nan_grad_frac": float(torch.isnan(bw[1]).double().mean().item())}
+    # the same persistent flash captured once into a HIP graph and replayed
+    if args.graph:
+        g = torch.cuda.CUDAGraph()
+        gs = torch.cuda.Stream()
+        gs.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(gs):
+            with torch.cuda.graph(g, stream=gs):
+                api.flash(z, T, P, Tc, Pc, om, kij, out=out)
+        torch.cuda.current_stream().wait_stream(gs)
+        g.replay()
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for _ in range(args.steps):
+            g.replay()
+        torch.cuda.synchronize()
+        wall_g = time.perf_counter() - tg
+        rec["graph_replay"] = {"value": w.n * args.steps / wall_g, "unit": "flashes/s",
+                               "ms_per_step": wall_g * 1e3 / args.steps}
     if args.plain_steps > 0:
         api.flash(z, T, P, Tc, Pc, om, kij, form=_capi.FORM_PLAIN, out=out)
         torch.cuda.synchronize()
