@@ -375,7 +375,7 @@ struct PreSsItem {
     int64_t m;
     double z[NC], d[NC], lk[NC];
     Eos<NC> e;
-    double theta;
+    double theta, zx, zy;   // zx, zy: Z of the previous evaluations
     int npre, steps;
     uint32_t fl;
 
@@ -395,6 +395,7 @@ struct PreSsItem {
         theta = 0.5;
         npre = 0;
         steps = 0;
+        zx = zy = -1.0;
         return true;
     }
 
@@ -410,11 +411,13 @@ struct PreSsItem {
             return true;
         }
         Phase<NC> o;
-        phase_eval<NC>(o, e, pp.K, w0, fl);
+        phase_eval<NC>(o, e, pp.K, w0, fl, zx);
+        zx = o.Z;
         double r0[NC];
 #pragma unroll
         for (int i = 0; i < NC; ++i) r0[i] = o.lnphi[i];
-        phase_eval<NC>(o, e, pp.K, w1, fl);
+        phase_eval<NC>(o, e, pp.K, w1, fl, zy);
+        zy = o.Z;
 #pragma unroll
         for (int i = 0; i < NC; ++i) lk[i] = r0[i] - o.lnphi[i];
         fl += NC;
@@ -451,7 +454,7 @@ struct SaSsItem {
     int t;
     double lw[NC], prev[NC], d[NC];
     Eos<NC> e;
-    double tmb, ext;
+    double tmb, ext, zw;   // zw: Z of the previous evaluation (cubic start)
     bool dem;
     int ss, steps;
     uint32_t fl, st;
@@ -473,6 +476,7 @@ struct SaSsItem {
         ss = 0;
         steps = 0;
         dem = false;
+        zw = -1.0;
         return true;
     }
 
@@ -498,7 +502,8 @@ struct SaSsItem {
         for (int i = 0; i < NC; ++i) W[i] = exp(lw[i]);
         fl += NC;
         Phase<NC> o;
-        phase_eval<NC>(o, e, pp.K, W, fl);
+        phase_eval<NC>(o, e, pp.K, W, fl, zw);
+        zw = o.Z;
         double grad[NC], tm = 1.0, gmax = 0.0;
 #pragma unroll
         for (int i = 0; i < NC; ++i) {
@@ -553,7 +558,7 @@ struct SaTrItem {
     int t;
     double lw[NC], lacc[NC], d[NC];
     Eos<NC> e;
-    double rad, facc, pred, gacc;
+    double rad, facc, pred, gacc, zw;   // zw: Z of the previous evaluation
     bool pend;
     int tr, steps;
     uint32_t fl, st;
@@ -576,6 +581,7 @@ struct SaTrItem {
         pend = false;
         tr = 0;
         steps = 0;
+        zw = -1.0;
         return true;
     }
 
@@ -599,7 +605,8 @@ struct SaTrItem {
         for (int i = 0; i < NC; ++i) W[i] = exp(lw[i]);
         fl += NC;
         Phase<NC> o;
-        phase_eval<NC>(o, e, pp.K, W, fl);
+        phase_eval<NC>(o, e, pp.K, W, fl, zw);
+        zw = o.Z;
         double F[NP], Hs[NP], dinv[NC];
         phase_derivs<NC>(F, o, e, pp.K, fl);
         double grad[NC], g[NC], tm = 1.0, sw = 0.0, gmax = 0.0;
@@ -743,7 +750,7 @@ struct SpSsItem {
     int64_t m;
     double z[NC], lk[NC], prev[NC];
     Eos<NC> e;
-    double theta, sgb, sext;
+    double theta, sgb, sext, zx, zy;   // zx, zy: Z of the previous evaluations
     bool dem;
     int ss, steps;
     uint32_t fl, status;
@@ -765,6 +772,7 @@ struct SpSsItem {
         ss = 0;
         steps = 0;
         dem = false;
+        zx = zy = -1.0;
         return true;
     }
 
@@ -787,11 +795,13 @@ struct SpSsItem {
             return true;
         }
         Phase<NC> o;
-        phase_eval<NC>(o, e, pp.K, x, fl);
+        phase_eval<NC>(o, e, pp.K, x, fl, zx);
+        zx = o.Z;
         double r0[NC];
 #pragma unroll
         for (int i = 0; i < NC; ++i) r0[i] = o.lnphi[i];
-        phase_eval<NC>(o, e, pp.K, y, fl);
+        phase_eval<NC>(o, e, pp.K, y, fl, zy);
+        zy = o.Z;
         // G per unit feed (eq. gibbs) where an acceleration check needs it
         const bool dem_next = a.dem_every > 0 && ss + 1 >= 2 && ((ss + 1) % a.dem_every) == 0;
         double G = 0.0;
@@ -858,7 +868,7 @@ struct SpNtItem {
     int64_t m;
     double z[NC], v0[NC], v1[NC];
     Eos<NC> e;
-    double srad, sfacc, spred, sgacc, sdprev;
+    double srad, sfacc, spred, sgacc, sdprev, zx, zy;   // zx, zy: previous Z
     bool spend, spol;
     int tr, pol, steps;
     uint32_t fl, status;
@@ -879,6 +889,7 @@ struct SpNtItem {
         srad = 0.0;
         spend = spol = false;
         tr = pol = steps = 0;
+        zx = zy = -1.0;
         return true;
     }
 
@@ -962,7 +973,8 @@ struct SpNtItem {
         fl += 4 * NC;
         double F[NP], Hs[NP], dinv[NC];
         Phase<NC> o;
-        phase_eval<NC>(o, e, pp.K, w0, fl);
+        phase_eval<NC>(o, e, pp.K, w0, fl, zx);
+        zx = o.Z;
         phase_derivs<NC>(F, o, e, pp.K, fl);
 #pragma unroll
         for (int i = 0; i < NC; ++i)
@@ -973,7 +985,8 @@ struct SpNtItem {
         const double Z0 = o.Z;
 #pragma unroll
         for (int i = 0; i < NC; ++i) r0[i] = o.lnphi[i];
-        phase_eval<NC>(o, e, pp.K, w1, fl);
+        phase_eval<NC>(o, e, pp.K, w1, fl, zy);
+        zy = o.Z;
         phase_derivs<NC>(F, o, e, pp.K, fl);
         const double th = bvap;
         // gradient of G over n^V (eq. split_grad) and G itself (eq. gibbs)

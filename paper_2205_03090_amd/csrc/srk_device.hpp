@@ -81,7 +81,11 @@ struct Phase {
 };
 
 // Minimum-Gibbs root of Z^3 - Z^2 + (A - B - B^2) Z - AB = 0 (eq. cubic_Z).
-// Halley's iteration (eq. halley) from the liquid-like start Z = B, kept
+// Halley's iteration (eq. halley) from the liquid-like start Z = B (or from
+// zs, the root chosen at the previous iterate of the same phase, when it lies
+// inside the bracket: deflation recovers the other roots from whichever root
+// the iteration reaches, so the root set and the choice below do not depend
+// on the start), kept
 // inside the sign-change bracket [B, 1+B] (f(B) = -2B^2 < 0, f(1+B) = A > 0),
 // stopping when a Halley step is below 1e-8 Z or at an exact zero of f;
 // deflation to a quadratic for the other
@@ -90,11 +94,12 @@ struct Phase {
 // (vapour) root the one with the lower reduced residual Gibbs energy
 // g = Z - 1 - ln(Z - B) - (A/B) ln(1 + B/Z) is kept (ties go to the liquid).
 __device__ __forceinline__ void cubic_root(double A, double B, double &Zout, double &Lout,
-                                           double &lzbout, int &nroots, uint32_t &fl)
+                                           double &lzbout, int &nroots, uint32_t &fl,
+                                           double zs = -1.0)
 {
     const double r1 = A - B * (1.0 + B);
     const double r0 = A * B;
-    double lo = B, hi = 1.0 + B, Z = B;
+    double lo = B, hi = 1.0 + B, Z = (zs > B && zs < 1.0 + B) ? zs : B;
     int it = 0;
     for (; it < 96; ++it) {
         const double f = ((Z - 1.0) * Z + r1) * Z - r0;
@@ -171,7 +176,7 @@ __device__ __forceinline__ void cubic_root(double A, double B, double &Zout, dou
 template <int NC>
 __device__ __forceinline__ void phase_eval(Phase<NC> &o, const Eos<NC> &e,
                                            const double *__restrict__ K, const double (&w)[NC],
-                                           uint32_t &fl)
+                                           uint32_t &fl, double zs = -1.0)
 {
     double sum = 0.0;
 #pragma unroll
@@ -201,7 +206,7 @@ __device__ __forceinline__ void phase_eval(Phase<NC> &o, const Eos<NC> &e,
         B += c[i] * e.b[i];
     }
     fl += Cost<NC>::mix;
-    cubic_root(A, B, o.Z, o.L, o.lzb, o.nroots, fl);
+    cubic_root(A, B, o.Z, o.L, o.lzb, o.nroots, fl, zs);
     o.A = A;
     o.B = B;
     const double ib = 1.0 / B;
