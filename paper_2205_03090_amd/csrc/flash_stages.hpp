@@ -63,7 +63,7 @@ struct MixRec {
     double lnz[NC];        // ln of the normalised feed
     double d[NC];          // ln z + ln phi(z)
     double lkw[NC];        // Wilson ln K
-    double lk[NC];         // split ln K (Pre case 3, SaFin), then n^V (SpSs -> SpNt)
+    double lk[NC];         // split ln K (PreSs case 3, SaFin), then n^V (SpSs -> SpNt)
     double lw[2][NC];      // ln W of the stability trials (start of SaTr, final)
     double tm[2];          // final tm of the trials
     double theta;          // Rachford-Rice warm start
