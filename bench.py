@@ -6,7 +6,8 @@ throughput of the persistent form; `fwd_adjoint` times forward (keeping the
 factor) + implicit-function backward; `plain_form` times the plain
 one-launch-per-stage-iteration form on the same inputs.
 
-  python bench.py [--steps K] [--warmup W] [--workload nc8_1m|nc3_10k|nc10_1m|nc20_8m]
+  python bench.py [--steps K] [--warmup W]
+                  [--workload nc8_1m|nc3_10k|nc10_1m|nc20_8m|cs2_10m|cs4_5m|cs9_1m]
                   [--form persistent|plain] [--no-cpu-baseline] [--no-adjoint]
                   [--plain-steps N] [--check M]
 """
@@ -106,7 +107,11 @@ def main():
     from paper_2205_03090_amd import _capi, api, workloads
 
     makers = {"nc8_1m": workloads.nc8_workload, "nc3_10k": workloads.nc3_workload,
-              "nc10_1m": workloads.nc10_workload, "nc20_8m": workloads.nc20_workload}
+              "nc10_1m": workloads.nc10_workload, "nc20_8m": workloads.nc20_workload,
+              # the paper's case studies at its largest sizes (Sec. 5.1)
+              "cs2_10m": lambda: workloads.case_study_workload("cs2", 10_000_000),
+              "cs4_5m": lambda: workloads.case_study_workload("cs4", 5_000_000),
+              "cs9_1m": lambda: workloads.case_study_workload("cs9", 1_000_000)}
     w = makers[args.workload]()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)

@@ -104,9 +104,9 @@ typedef struct {
     int32_t max_pre_ss;    /* 3: initial split substitutions (Sec. 2.2.3)       */
     int32_t max_ss;        /* 9: substitution cap, stability and split (2.2.1-2) */
     int32_t max_tr_sa;     /* 20: stability trust-region cap (Algorithm 2)      */
-    int32_t max_tr_split;  /* 20: split trust-region cap                         */
+    int32_t max_tr_split;  /* 30: split trust-region cap                         */
     int32_t max_polish;    /* 4: Newton refinement steps after convergence       */
-    int32_t dem_every;     /* 5: dominant-eigenvalue acceleration period, 0 off  */
+    int32_t dem_every;     /* 3: dominant-eigenvalue acceleration period, 0 off  */
     double tol_sa_ss;      /* 1e-6: max |d tm/d W| (Sec. 2.2.1)                 */
     double tol_sa_tr;      /* 1e-6: max |g| of the stability trust region (B.1) */
     double tol_split_ss;   /* 1e-8: max |K_new/K - 1| (Sec. 2.2.2)              */

@@ -28,7 +28,7 @@ class OrcOpts(C.Structure):
 
 
 INFO_FIELDS = ["case", "pre", "ss_v", "nt_v", "ss_l", "nt_l", "ss_split",
-               "nt_split", "flags", "out_v", "out_l", "swap"]
+               "nt_split", "flags", "out_v", "out_l", "swap", "split_ss_conv"]
 FLAG_INVALID, FLAG_SA_UNCONV, FLAG_SPLIT_UNCONV = 1, 2, 4
 FLAG_SPLIT_TRIVIAL, FLAG_SPLIT_FAILED, FLAG_RR_NO_ROOT = 8, 16, 32
 

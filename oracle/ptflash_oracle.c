@@ -34,14 +34,19 @@
  *       eq. tm), so that tm = 0 at the trivial point W = z.
  *   R2  Delta G of the initial triage = (1-theta) tpd(x) + theta tpd(y)
  *       (Sec. 2.2.3); with theta in (0,1) it is a convex combination.
- *   R3  dominant-eigenvalue acceleration: at every 5th successive
+ *   R3  dominant-eigenvalue acceleration: at every 3rd successive
  *       substitution update u (u >= 2), lambda = (s_u . s_u)/(s_{u-1} . s_u)
  *       with s the plain update step; if 0 < lambda < 1 the update is
  *       extended by s_u lambda/(1-lambda).  The extrapolated point is kept
  *       only if its objective (tm for a stability trial, G per unit feed for
- *       the split) is lower than at the point the update started from;
- *       otherwise the plain update is taken (the rejected evaluation is not
- *       counted).  Not applied in the three initial iterations.
+ *       the split) is lower than at the point the update started from, and,
+ *       in the split, only if its Rachford-Rice root lies in (0,1) (where G
+ *       is the Gibbs energy of two phases); otherwise the plain update is
+ *       taken (the rejected evaluation is not counted).  A split update
+ *       after which the substitution stops is never extended.  Not applied
+ *       in the three initial iterations.  Period 3 is the one whose
+ *       substitution convergence rates on the nine-component case study
+ *       come closest to those of Table 5.
  *   R4  a stability trial is unstable when tm < -eps_tm (eps_tm = 1e-10).
  *   R5  trials start from the Wilson K; the initial successive substitution
  *       stops at the first iteration whose Rachford-Rice root leaves (0,1)
@@ -79,7 +84,7 @@ typedef struct {
     int32_t max_pre_ss;      /* initial phase-split substitutions (3)      */
     int32_t max_ss;          /* successive-substitution cap (9)            */
     int32_t max_newton;      /* cap of the oracle's Newton stand-ins       */
-    int32_t dem_every;       /* acceleration period (5), 0 = off           */
+    int32_t dem_every;       /* acceleration period (3), 0 = off           */
     int32_t want_min_tpd;    /* also compute the min-TPD diagnostic        */
     int32_t max_newton_split;/* cap of the split's Newton stand-in         */
     double tol_sa_ss;        /* max |d tm / d W| (1e-6)                    */
@@ -101,7 +106,7 @@ typedef struct {
 enum {
     ORC_I_CASE = 0, ORC_I_PRE, ORC_I_SS_V, ORC_I_NT_V, ORC_I_SS_L, ORC_I_NT_L,
     ORC_I_SS_SPLIT, ORC_I_NT_SPLIT, ORC_I_FLAGS, ORC_I_OUT_V, ORC_I_OUT_L,
-    ORC_I_NROOT_SWAP, ORC_NINFO
+    ORC_I_NROOT_SWAP, ORC_I_SPLIT_SS_CONV, ORC_NINFO
 };
 
 /* ---------------------------------------------------------------------- */
@@ -663,7 +668,17 @@ static int orc_split_ss(const orc_eos *e, const double *z, double *lnK,
     for (int guard = 0; guard < 4 * o->max_ss + 8 && u < o->max_ss; ++guard) {
         double th;
         for (int i = 0; i < nc; ++i) K[i] = exp(lnK[i]);
-        if (orc_rr_solve(nc, z, K, &th) != 0) { *rr_fail = 1; return u; }
+        if (orc_rr_solve(nc, z, K, &th) != 0) {
+            if (pending) {
+                /* R3: an extrapolated point without a Rachford-Rice root is
+                 * rejected like one that does not lower G */
+                pending = 0;
+                for (int i = 0; i < nc; ++i) lnK[i] -= ext_applied * prev[i];
+                continue;
+            }
+            *rr_fail = 1;
+            return u;
+        }
         orc_xy_from_k(nc, z, K, th, x, y);
         orc_phase(e, x, lx, NULL);
         orc_phase(e, y, ly, NULL);
@@ -674,9 +689,11 @@ static int orc_split_ss(const orc_eos *e, const double *z, double *lnK,
                 G += (1.0 - th) * x[i] * (log(x[i]) + lx[i]) + th * y[i] * (log(y[i]) + ly[i]);
         }
         if (pending) {
-            /* R3: an extrapolated point is kept only if it lowers G */
+            /* R3: an extrapolated point is kept only if it is a physical
+             * split (0 < theta < 1, where eq. gibbs is the Gibbs energy of
+             * two phases) and lowers G */
             pending = 0;
-            if (!(G < g_before)) {
+            if (!(th > 0.0 && th < 1.0 && G < g_before)) {
                 for (int i = 0; i < nc; ++i) lnK[i] -= ext_applied * prev[i];
                 continue;
             }
@@ -688,8 +705,12 @@ static int orc_split_ss(const orc_eos *e, const double *z, double *lnK,
             if (q > dmax) dmax = q;
         }
         ++u;
+        /* R3: no extension on an update after which the substitution stops
+         * (converged or out of budget), since no later evaluation could
+         * check the extrapolated point */
+        int more = !(dmax < o->tol_split_ss) && u < o->max_ss;
         double ext = 0.0;
-        if (o->dem_every > 0 && u >= 2 && u % o->dem_every == 0) {
+        if (more && o->dem_every > 0 && u >= 2 && u % o->dem_every == 0) {
             double num = 0.0, den = 0.0;
             for (int i = 0; i < nc; ++i) { num += step[i] * step[i]; den += prev[i] * step[i]; }
             double lam = num / den;
@@ -899,6 +920,7 @@ int orc_flash_one(int nc, const double *z_in, double T, double P,
     int conv = 0, rrf = 0;
     int nss = orc_split_ss(&e, z, lnK, o, &conv, &rrf);
     res->info[ORC_I_SS_SPLIT] = nss;
+    res->info[ORC_I_SPLIT_SS_CONV] = conv;
     double thf;
     for (int i = 0; i < nc; ++i) K[i] = exp(lnK[i]);
     if (rrf || orc_rr_solve(nc, z, K, &thf) != 0) {
@@ -959,7 +981,7 @@ void orc_default_opts(orc_opts *o)
     o->max_pre_ss = 3;
     o->max_ss = 9;
     o->max_newton = 200;
-    o->dem_every = 5;
+    o->dem_every = 3;
     o->want_min_tpd = 0;
     o->max_newton_split = 200;
     o->tol_sa_ss = 1e-6;

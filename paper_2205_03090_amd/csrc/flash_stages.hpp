@@ -28,6 +28,9 @@
 //     s_u lambda/(1 - lambda) when 0 < lambda < 1, kept only if the
 //     extrapolated point lowers the objective (tm, or G per unit feed),
 //     otherwise replaced by the plain update (not counted as an iteration);
+//     in the split, the extrapolated point must also have a Rachford-Rice
+//     root in (0,1), and no extension follows an update after which the
+//     substitution stops;
 //   * the trials start from the Wilson K, the initial substitutions stop at
 //     the first Rachford-Rice root outside (0,1) (case 1), and a case-3 split
 //     continues from the latest K with a fresh substitution budget;
@@ -791,6 +794,14 @@ struct SpSsItem {
         const FlashArgs &a = c.a;
         double x[NC], y[NC];
         if (!xy_from_lnk<NC>(x, y, lk, z, theta, fl)) {
+            if (dem) {
+                // an extrapolated point without a Rachford-Rice root is
+                // rejected like one that does not lower G
+                dem = false;
+#pragma unroll
+                for (int i = 0; i < NC; ++i) lk[i] -= sext * prev[i];
+                if (++steps < kStepGuard) return false;
+            }
             fail(c, kStRrNoRoot | kStSplitFailed);
             return true;
         }
@@ -812,9 +823,11 @@ struct SpSsItem {
             fl += 10 * NC;
         }
         if (dem) {
-            // an extrapolated point is kept only if it lowers G
+            // an extrapolated point is kept only if it is a physical split
+            // (0 < theta < 1, where G is the Gibbs energy of two phases) and
+            // lowers G
             dem = false;
-            if (!(G < sgb)) {
+            if (!(theta > 0.0 && theta < 1.0 && G < sgb)) {
 #pragma unroll
                 for (int i = 0; i < NC; ++i) lk[i] -= sext * prev[i];
                 if (++steps < kStepGuard) return false;
@@ -827,10 +840,14 @@ struct SpSsItem {
             dmax = fmax(dmax, fabs(exp(s[i]) - 1.0));
         }
         fl += 4 * NC;
-        const double ext = ss_update<NC>(lk, prev, s, ss + 1, a.dem_every, fl);
-        ++ss;
+        // no extension on an update after which the substitution stops: no
+        // later evaluation could check the extrapolated point
         const bool conv = dmax < a.tol_split_ss;
-        if (!conv && ss < a.max_ss && ++steps < kStepGuard) {
+        const bool more = !conv && ss + 1 < a.max_ss && steps + 1 < kStepGuard;
+        const double ext = ss_update<NC>(lk, prev, s, ss + 1, more ? a.dem_every : 0, fl);
+        ++ss;
+        if (more) {
+            ++steps;
             if (ext > 0.0) {
                 dem = true;
                 sgb = G;

@@ -321,9 +321,9 @@ void ptflash_default_options(ptflash_options *o)
     o->max_pre_ss = 3;
     o->max_ss = 9;
     o->max_tr_sa = 20;
-    o->max_tr_split = 20;
+    o->max_tr_split = 30;
     o->max_polish = 4;
-    o->dem_every = 5;
+    o->dem_every = 3;
     o->tol_sa_ss = 1e-6;
     o->tol_sa_tr = 1e-6;
     o->tol_split_ss = 1e-8;

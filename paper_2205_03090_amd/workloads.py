@@ -15,10 +15,10 @@ bytes without sharing any thermodynamics.  Every draw uses NumPy's
 With ``per_mixture`` the component set of step 1 is drawn per mixture (n
 sets, each in the same field order: all Tc, all Pc, all omega, all k).
 
-The paper's own workloads (Sec. 2.3-2.4: Table 1 components, Latin
-hypercube + Dirichlet sampling) are replaced by these random-property
-workloads; the distributions follow the paper's ranges of T and P and its
-Dirichlet feed.
+These random-property workloads follow the paper's ranges of T and P and
+its Dirichlet feed.  The paper's own three case studies (Sec. 2.3-2.4:
+Table 1 components, Latin hypercube + Dirichlet sampling, Tables 2 and 3
+for the nine-component fluids) are built by ``case_study_workload``.
 """
 from __future__ import annotations
 
@@ -169,3 +169,190 @@ def ragged_workload(name: str, seed: int, n: int, nc_set=(2, 4, 6, 8, 12, 16, 20
     T = rng.uniform(T_range[0], T_range[1], n)
     P = rng.uniform(P_range[0], P_range[1], n)
     return RaggedWorkload(name, n, nc_of, off, koff, z, T, P, Tc, Pc, om, kij)
+
+
+# ---------------------------------------------------------------------------
+# The paper's case studies (Sec. 2.3 "Case studies", Sec. 2.4 "Data
+# generation").
+# ---------------------------------------------------------------------------
+
+# Table 1: name, Pc [MPa], Tc [K], acentric factor.
+PAPER_COMPONENTS = (
+    ("CH4", 4.6, 190.55, 0.0111),
+    ("C2H6", 4.875, 305.43, 0.097),
+    ("C3H8", 4.268, 369.82, 0.1536),
+    ("nC4H10", 3.796, 425.16, 0.2008),
+    ("nC5H12", 3.3332, 467.15, 0.2635),
+    ("C6H14", 2.9688, 507.4, 0.296),
+    ("C7H16+", 2.622, 604.5, 0.3565),
+    ("CO2", 7.382, 304.19, 0.225),
+    ("N2", 3.3944, 126.25, 0.039),
+)
+# Sec. 2.3: the only non-zero binary interaction parameter.
+KIJ_CH4_CO2 = 0.0882
+
+# Sec. 2.3: the components of the three case studies and their T, P boxes.
+CASE_STUDIES = {
+    "cs2": (("CH4", "C6H14"), (200.0, 500.0), (1.0e5, 1.0e7)),
+    "cs4": (("CH4", "C2H6", "C3H8", "nC4H10"), (200.0, 500.0), (1.0e5, 1.0e7)),
+    "cs9": (tuple(c[0] for c in PAPER_COMPONENTS), (200.0, 600.0), (5.0e6, 2.5e7)),
+}
+
+FLUIDS = ("wet_gas", "gas_condensate", "volatile_oil", "black_oil")
+
+# Table 2: mole-fraction box of each fluid type, in the order of Table 1.
+FLUID_RANGES = {
+    "wet_gas": ((0.80, 1.00), (0.02, 0.07), (0.0, 0.03), (0.0, 0.02), (0.0, 0.02),
+                (0.0, 0.02), (0.0, 0.01), (0.0, 0.02), (0.0, 0.005)),
+    "gas_condensate": ((0.60, 0.80), (0.05, 0.10), (0.0, 0.04), (0.0, 0.03), (0.0, 0.02),
+                       (0.0, 0.02), (0.05, 0.10), (0.0, 0.035), (0.0, 0.005)),
+    "volatile_oil": ((0.50, 0.70), (0.06, 0.10), (0.0, 0.045), (0.0, 0.03), (0.0, 0.02),
+                     (0.0, 0.02), (0.10, 0.30), (0.0, 0.02), (0.0, 0.005)),
+    "black_oil": ((0.20, 0.40), (0.03, 0.06), (0.0, 0.015), (0.0, 0.015), (0.0, 0.01),
+                  (0.0, 0.02), (0.45, 0.65), (0.0, 0.001), (0.0, 0.005)),
+}
+
+# Table 3: Dirichlet concentrations (CH4, C2H6, C7H16+); every other
+# component has concentration 1.
+FLUID_ALPHA = {
+    "wet_gas": (100.0, 5.0, 1.0),
+    "gas_condensate": (40.0, 5.0, 5.0),
+    "volatile_oil": (55.0, 8.0, 20.0),
+    "black_oil": (25.0, 4.0, 40.0),
+}
+
+CASE_SEEDS = {"cs2": 20_250_011, "cs4": 20_250_012, "cs9": 20_250_013}
+
+
+@dataclass
+class CaseStudyWorkload(Workload):
+    fluid: np.ndarray = None   # (n,) int8 index into FLUIDS (nine components), else None
+
+
+def case_components(names):
+    """Tc, Pc, omega and k of the named Table 1 components (k = 0 except
+    for the CH4-CO2 pair)."""
+    table = {c[0]: c for c in PAPER_COMPONENTS}
+    Tc = np.array([table[n][2] for n in names])
+    Pc = np.array([table[n][1] for n in names]) * 1.0e6
+    om = np.array([table[n][3] for n in names])
+    k = np.zeros((len(names), len(names)))
+    for a, na in enumerate(names):
+        for b, nb in enumerate(names):
+            if {na, nb} == {"CH4", "CO2"}:
+                k[a, b] = KIJ_CH4_CO2
+    return Tc, Pc, om, k
+
+
+def latin_hypercube(rng: np.random.Generator, m: int, d: int) -> np.ndarray:
+    """m points of a Latin hypercube in [0, 1)^d: in every dimension each of
+    the m strata [i/m, (i+1)/m) holds exactly one point, placed uniformly in
+    it.  Per dimension: one permutation, then m uniforms."""
+    u = np.empty((m, d))
+    for j in range(d):
+        u[:, j] = (rng.permutation(m) + rng.random(m)) / m
+    return u
+
+
+def fluid_alpha(fluid: str) -> np.ndarray:
+    a = np.ones(len(PAPER_COMPONENTS))
+    a[0], a[1], a[6] = FLUID_ALPHA[fluid]
+    return a
+
+
+def _lead_component(alpha: np.ndarray, box: np.ndarray) -> int:
+    """Among the components with concentration 1, the one whose box has the
+    smallest marginal probability (Beta(1, A - 1), CDF 1 - (1 - x)^(A - 1))."""
+    b = alpha.sum() - 1.0
+    best, arg = 2.0, -1
+    for j in range(len(alpha)):
+        if alpha[j] != 1.0:
+            continue
+        p = (1.0 - box[j, 0]) ** b - (1.0 - box[j, 1]) ** b
+        if p < best:
+            best, arg = p, j
+    return arg
+
+
+def truncated_dirichlet(rng: np.random.Generator, alpha: np.ndarray, box: np.ndarray,
+                        m: int, batch: int = 1 << 18) -> np.ndarray:
+    """m draws of Dirichlet(alpha) conditioned on lo_i <= z_i <= hi_i for all
+    i (box[i] = (lo_i, hi_i)): the feeds the paper keeps after rejecting
+    Dirichlet samples outside a fluid type's box.
+
+    Exact rejection sampling, with one shortcut: a lead component j of
+    concentration 1 is drawn from its marginal Beta(1, A - 1) (A = sum alpha)
+    restricted to its interval, by the closed-form inverse CDF, and the rest
+    as (1 - z_j) v with v ~ Dirichlet(alpha without j), which is independent
+    of z_j (Dirichlet neutrality).  The density of a draw is then the
+    Dirichlet density times the indicator of z_j's interval over a constant,
+    so rejecting draws that leave the box of the other components yields the
+    box-restricted Dirichlet, with fewer rejections than plain rejection.
+
+    Per batch, in this order: ``batch`` uniforms for z_j, then one
+    ``rng.dirichlet`` call for v."""
+    nc = len(alpha)
+    j = _lead_component(alpha, box)
+    rest = np.array([i for i in range(nc) if i != j])
+    b = alpha.sum() - 1.0
+    F = lambda x: 1.0 - (1.0 - x) ** b
+    flo, fhi = F(box[j, 0]), F(box[j, 1])
+    out, have = np.empty((m, nc)), 0
+    while have < m:
+        u = flo + (fhi - flo) * rng.random(batch)
+        zj = 1.0 - (1.0 - u) ** (1.0 / b)
+        v = rng.dirichlet(alpha[rest], size=batch)
+        z = np.empty((batch, nc))
+        z[:, j] = zj
+        z[:, rest] = (1.0 - zj)[:, None] * v
+        ok = np.all((z >= box[:, 0]) & (z <= box[:, 1]), axis=1) & np.all(z > 0.0, axis=1)
+        take = z[ok][: m - have]
+        out[have:have + len(take)] = take
+        have += len(take)
+    return out
+
+
+def case_study_workload(case: str, n: int, seed: int | None = None) -> CaseStudyWorkload:
+    """One of the paper's three case studies (Sec. 2.3-2.4), seeded.
+
+    cs2 (CH4, C6H14) and cs4 (CH4, C2H6, C3H8, nC4H10): P in [0.1, 10] MPa,
+    T in [200, 500] K, z over the whole simplex.  One Latin hypercube of n
+    points in (P, T, u_1 .. u_nc); y_i = Gamma(1, 1) quantile of u_i
+    (= -ln(1 - u_i)), z = y / sum y, i.e. z ~ Dirichlet(1).
+
+    cs9 (all Table 1 components, k(CH4, CO2) = 0.0882): P in [5, 25] MPa,
+    T in [200, 600] K; the four fluid types equally represented (n // 4 each,
+    the first n % 4 types one more), each z ~ Dirichlet(Table 3 alpha)
+    restricted to the type's Table 2 box (``truncated_dirichlet``), types in
+    the order of FLUIDS; then one permutation shuffles the rows and one Latin
+    hypercube of n points in (P, T) gives the conditions.  The paper draws
+    z from the same hypercube as P and T and then rejects; at the acceptance
+    rates of these boxes (about 0.1 % to 14 %) the kept feeds follow the
+    box-restricted Dirichlet, which is drawn here directly."""
+    names, (T_lo, T_hi), (P_lo, P_hi) = CASE_STUDIES[case]
+    seed = CASE_SEEDS[case] if seed is None else seed
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Tc, Pc, om, k = case_components(names)
+    nc = len(names)
+    fluid = None
+    if case != "cs9":
+        u = latin_hypercube(rng, n, 2 + nc)
+        y = -np.log1p(-u[:, 2:])
+        z = y / y.sum(axis=1, keepdims=True)
+        P = P_lo + (P_hi - P_lo) * u[:, 0]
+        T = T_lo + (T_hi - T_lo) * u[:, 1]
+    else:
+        parts, tags = [], []
+        for f, name in enumerate(FLUIDS):
+            m = n // 4 + (1 if f < n % 4 else 0)
+            parts.append(truncated_dirichlet(rng, fluid_alpha(name),
+                                             np.asarray(FLUID_RANGES[name]), m))
+            tags.append(np.full(m, f, dtype=np.int8))
+        perm = rng.permutation(n)
+        z = np.concatenate(parts)[perm]
+        fluid = np.concatenate(tags)[perm]
+        u = latin_hypercube(rng, n, 2)
+        P = P_lo + (P_hi - P_lo) * u[:, 0]
+        T = T_lo + (T_hi - T_lo) * u[:, 1]
+    return CaseStudyWorkload(f"{case}_{n}", n, nc, np.ascontiguousarray(z), T, P, Tc, Pc,
+                             om, k, False, fluid)

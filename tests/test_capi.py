@@ -28,9 +28,9 @@ def test_header_declarations_are_exported():
 
 def test_default_options_are_the_papers():
     o = _capi.default_options()
-    assert (o.max_pre_ss, o.max_ss, o.max_tr_sa, o.max_tr_split) == (3, 9, 20, 20)
+    assert (o.max_pre_ss, o.max_ss, o.max_tr_sa, o.max_tr_split) == (3, 9, 20, 30)
     assert (o.tol_sa_ss, o.tol_sa_tr, o.tol_split_ss, o.tol_split_tr) == (1e-6, 1e-6, 1e-8, 1e-8)
-    assert o.dem_every == 5 and o.eps_tm == 1e-10 and o.form == _capi.FORM_PERSISTENT
+    assert o.dem_every == 3 and o.eps_tm == 1e-10 and o.form == _capi.FORM_PERSISTENT
 
 
 def test_rejects_malformed_calls_without_gpu():

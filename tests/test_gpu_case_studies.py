@@ -1,0 +1,98 @@
+"""GPU parity and stage statistics on the paper's three case studies
+(Sec. 2.3-2.4): CH4/C6H14, CH4-nC4H10 and the nine Table 1 components with
+the four fluid types of Tables 2-3.
+
+Parity on 20,000 mixtures of each case (many wavefronts, a ragged tail);
+the plain form against the persistent one on the nine-component case; and
+the share of mixtures each stage settles at the paper's n = 1e6 against
+Table 5, from the GPU's own iteration counters and status bits.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_2205_03090_amd import _capi, api, workloads  # noqa: E402
+from paper_tables import table5  # noqa: E402
+from parity import compare, gpu_to_numpy, invariants  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+IT = {k: i for i, k in enumerate(_capi.IT_NAMES)}
+ST = _capi.ST
+
+
+def _run(w, **kw):
+    r = api.flash(w.z, w.T, w.P, w.Tc, w.Pc, w.omega, w.kij, **kw)
+    torch.cuda.synchronize()
+    return gpu_to_numpy(r)
+
+
+@pytest.mark.parametrize("case", ["cs2", "cs4", "cs9"])
+def test_case_study_parity(case):
+    w = workloads.case_study_workload(case, 20000)
+    print(f"case {case} n={w.n}", flush=True)
+    g = _run(w)
+    inv = invariants(w, g)
+    print(f"[{case} invariants] {inv}", flush=True)
+    assert inv["mass_balance"] < 1e-13 and inv["sum_x"] < 1e-13 and inv["sum_y"] < 1e-13
+    assert inv["single_ok"] and inv["beta_in_range"] and inv["labels_valid"]
+    o = oracle.flash(w, threads=8, want_min_tpd=1)
+    rep = compare(g, o, w=w)
+    print(f"[{case}] {rep}", flush=True)
+    assert rep["label_mismatch"] == 0
+    assert rep["value_mismatch"] == 0
+    assert rep["single_mismatch"] == 0
+    assert rep["ss_path_agree"] >= 0.99
+
+
+def test_cs9_plain_equals_persistent():
+    w = workloads.case_study_workload("cs9", 20000)
+    print(f"case cs9 plain vs persistent n={w.n}", flush=True)
+    a = _run(w)
+    b = _run(w, form=_capi.FORM_PLAIN)
+    for k in ("label", "beta", "x", "y", "iters", "status"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_table5_stage_shares_gpu():
+    # Shares of the mixtures that each stage settles, at the paper's size.
+    # The bands allow for what the paper leaves unprinted (acceleration
+    # rule, trust-region details, sampling seed); see the oracle's test of
+    # the same shares.
+    t5 = table5()
+    n = t5["initial_ss"][0]
+    w = workloads.case_study_workload("cs9", n)
+    print(f"case cs9 stage shares n={n}", flush=True)
+    g = _run(w)
+    it, st = g["iters"].astype(np.int64), g["status"].astype(np.int64) & 0xFFFF
+    assert not np.any(st & (ST["INVALID"] | ST["STEP_CAP"]))
+    pct = lambda b: 100.0 * np.mean(b)
+    shortcut = pct((st & ST["SHORTCUT"]) != 0)
+    sa = (st & ST["SA_RAN"]) != 0
+    ss_v, ss_l = pct(it[sa, IT["tr_v"]] == 0), pct(it[sa, IT["tr_l"]] == 0)
+    entered = it[:, IT["ss_split"]] > 0
+    split_tr = entered & ((st & ST["SPLIT_TR"]) != 0)
+    split = pct(entered)
+    split_ss = 100.0 - pct(split_tr[entered])
+    tr3 = pct(it[split_tr, IT["tr_split"]] <= 3)
+    mx = {k: int(it[:, IT[k]].max()) for k in ("tr_v", "tr_l", "tr_split")}
+    print(f"[cs9 table 5] shortcut {shortcut:.2f} % (paper {t5['initial_ss'][1]}); "
+          f"stability runs {int(sa.sum())} (paper {t5['sa_ss_vapour'][0]}), substitution "
+          f"V {ss_v:.2f} % L {ss_l:.2f} % (paper {t5['sa_ss_vapour'][1]} / "
+          f"{t5['sa_ss_liquid'][1]}); trust-region runs V {int((it[:, IT['tr_v']] > 0).sum())} "
+          f"L {int((it[:, IT['tr_l']] > 0).sum())} (paper {t5['sa_tr_vapour'][0]} / "
+          f"{t5['sa_tr_liquid'][0]}); split runs {int(entered.sum())} (paper "
+          f"{t5['split_ss'][0]}), substitution {split_ss:.2f} % (paper {t5['split_ss'][1]}); "
+          f"split trust region within 3 steps {tr3:.2f} % (paper 92.67); max steps {mx} "
+          f"(paper V {t5['sa_tr_vapour'][2]} L {t5['sa_tr_liquid'][2]} "
+          f"split {t5['split_tr'][2]})", flush=True)
+    assert abs(shortcut - t5["initial_ss"][1]) < 5.0
+    assert abs(ss_v - t5["sa_ss_vapour"][1]) < 10.0
+    assert abs(ss_l - t5["sa_ss_liquid"][1]) < 10.0
+    assert abs(split - 100.0 * t5["split_ss"][0] / n) < 6.0
+    assert abs(split_ss - t5["split_ss"][1]) < 12.0
+    assert it[:, IT["pre"]].max() <= 3
+    assert max(it[:, IT["ss_v"]].max(), it[:, IT["ss_l"]].max(), it[:, IT["ss_split"]].max()) <= 9
+    assert max(mx.values()) <= 20
