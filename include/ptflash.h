@@ -115,8 +115,15 @@ typedef struct {
     double eps_tm;         /* 1e-10: a trial is unstable when tm < -eps_tm       */
     int32_t form;          /* PTFLASH_FORM_*                                     */
     int32_t keep_factor;   /* 1: write the Cholesky factor for the backward     */
-    int32_t block;         /* threads per block, 0 = library default            */
+    int32_t block;         /* threads per block (64, 128, 256), 0 = tuned       */
     int32_t grid;          /* persistent blocks, 0 = fill the device            */
+    int32_t lanes_per_mixture; /* trust-region stages of the persistent form:
+                              0 = the library's tuned choice for nc, 1 = one
+                              mixture per lane, 16 or 32 = one group of that
+                              many lanes per mixture (lane i holds component
+                              i; needs 8 <= nc <= lanes).  Other values, or a
+                              group too small for nc: PTFLASH_EINVAL.  The
+                              plain form always runs one mixture per lane. */
 } ptflash_options;
 
 /* Outputs (device pointers).  label, beta, x, y are required; the others may

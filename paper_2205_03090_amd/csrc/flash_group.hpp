@@ -1,0 +1,728 @@
+// flash_group.hpp -- the two trust-region stages (stability trials, SaTr;
+// split, SpNt) with one group of G lanes per mixture, for the larger
+// component counts.
+//
+// With one mixture per lane, a trust-region iteration keeps the packed
+// Hessian, its Cholesky factor and the composition derivatives of two phases
+// per lane: 3 nc(nc+1)/2 doubles, which at nc = 20 is several KB per lane and
+// spills.  Here lane i of a group holds component i: its composition and
+// gradient entries, row i of the Hessian and row i of the factor.  Sums over
+// components are butterfly reductions inside the group (every lane ends with
+// the same bits: floating-point addition is commutative), vectors that every
+// row needs are broadcast through the group's LDS region, and the factor is
+// also kept there so that the back substitution can read its columns.  The
+// mixture's scalars (cubic root, trust radius, counters, decisions) are
+// computed identically in every lane of the group, so a group always takes
+// one path.  The arithmetic is that of the per-lane items in flash_stages.hpp
+// (Appendix B.1 and B.2, readings as listed there); only the order of the
+// sums differs.
+#pragma once
+
+#include "flash_stages.hpp"
+
+namespace ptf {
+
+// Component counts from which the group variants are compiled.
+constexpr int kGroupMinNc = 8;
+
+// LDS doubles of one group: the factor (nc + 1 rows of nc: row i of L, and
+// a spare row that the lanes beyond nc write to) and five broadcast vectors
+// of G entries.
+template <int NC, int G>
+struct GroupLds {
+    static constexpr int L = 0;
+    static constexpr int V = (NC + 1) * NC;
+    static constexpr int N = V + 5 * G;
+};
+
+// Orders the LDS accesses of one wavefront: stores before the fence are
+// visible to the loads after it (the lanes of a group are in one wavefront).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int G>
+__device__ __forceinline__ double gsum(double v)
+{
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int G>
+__device__ __forceinline__ double gmax(double v)
+{
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+template <int G>
+__device__ __forceinline__ double gmin(double v)
+{
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Value of lane j of the caller's group.
+__device__ __forceinline__ double gbcast(double v, int base, int j)
+{
+    return __shfl(v, base + j, 64);
+}
+
+// Lane geometry of a group and its LDS region.  The unrolled loops below
+// over components j never test gi against j (such tests are loop-invariant
+// lane masks that the compiler keeps live across the whole kernel): values
+// of one lane are broadcast from it, results are read back from LDS slots,
+// and the diagonal of a matrix row is carried separately.
+template <int NC, int G>
+struct Grp {
+    // all five fields are set by the kernel before the first item begins
+    int gi;       // component of this lane (valid below NC)
+    int row;      // gi, or NC (the spare factor row) beyond the components
+    int base;     // first lane of the group in the wavefront
+    bool act;     // gi < NC
+    double *sh;   // GroupLds<NC, G>::N doubles
+    __device__ __forceinline__ double *vec(int q) const { return sh + GroupLds<NC, G>::V + q * G; }
+    __device__ __forceinline__ double *lsh() const { return sh + GroupLds<NC, G>::L; }
+};
+
+// Phase evaluation E(c) of one mixture across its group: this lane's share is
+// component gi of the mole numbers w (0 on inactive lanes).  As phase_eval.
+struct PhaseG {
+    double A, B, Z, L, lzb, q1, q2;
+    int nroots;
+    double psi, lnphi;   // this lane's component
+};
+
+template <int NC, int G>
+__device__ __forceinline__ void phase_eval_g(PhaseG &o, const Grp<NC, G> &g, double s, double b,
+                                             const double (&kap)[NC], double w, uint32_t &fl,
+                                             double zs)
+{
+    const double sum = gsum<G>(w);
+    const double inv = 1.0 / sum;
+    const double c = w * inv;
+    const double t = s * c;
+    double *tv = g.vec(0);
+    tv[g.gi] = t;
+    wave_lds_sync();
+    double psi = 0.0;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) psi += kap[j] * tv[j];
+    wave_lds_sync();
+    const double A = gsum<G>(g.act ? t * psi : 0.0);
+    const double B = gsum<G>(c * b);
+    fl += Cost<NC>::mix;
+    cubic_root(A, B, o.Z, o.L, o.lzb, o.nroots, fl, zs);
+    o.A = A;
+    o.B = B;
+    const double ib = 1.0 / B;
+    o.q1 = (o.Z - 1.0 + A * ib * o.L) * ib;
+    o.q2 = 2.0 * o.L * ib;
+    o.psi = psi;
+    o.lnphi = b * o.q1 - o.lzb - o.q2 * s * psi;
+    fl += Cost<NC>::lnphi;
+}
+
+// Adds wrow * v_j * Phi_ij (row i = gi of Phi = n d ln phi / d n, as
+// phase_derivs) to hrow[j] for every j, and the diagonal term to hdiag (the
+// same bits as hrow[gi]); v is this lane's entry of the scaling vector (0 on
+// inactive lanes, where wrow is 0 too).
+template <int NC, int G>
+__device__ __forceinline__ void phase_derivs_g(double (&hrow)[NC], double &hdiag, const PhaseG &o,
+                                               const Grp<NC, G> &g, double s, double b,
+                                               const double (&kap)[NC], double wrow, double v,
+                                               uint32_t &fl)
+{
+    const double A = o.A, B = o.B, Z = o.Z, L = o.L;
+    const double fA = Z - B;
+    const double fB = -(1.0 + 2.0 * B) * Z - A;
+    const double fZ = (3.0 * Z - 2.0) * Z + A - B - B * B;
+    const double ifZ = 1.0 / fZ;
+    const double ib = 1.0 / B;
+    const double izzb = 1.0 / (Z * (Z + B));
+    const double izb = 1.0 / (Z - B);
+    const double sp = s * o.psi;
+    const double dA = 2.0 * (sp - A);
+    const double dB = b - B;
+    const double dZ = -(fA * dA + fB * dB) * ifZ;
+    const double dL = (Z * dB - B * dZ) * izzb;
+    const double be = (dZ - dB) * izb;
+    const double ga = 2.0 * (dL - L * dB * ib) * ib;
+    const double al = (dZ + (dA * L + A * dL) * ib - A * L * dB * ib * ib) * ib - o.q1 * dB * ib;
+    double *va = g.vec(0), *vb = g.vec(1), *vg = g.vec(2), *vs = g.vec(3), *vv = g.vec(4);
+    va[g.gi] = al;
+    vb[g.gi] = be;
+    vg[g.gi] = ga;
+    vs[g.gi] = s;
+    vv[g.gi] = v;
+    wave_lds_sync();
+    const double cst = o.q2 * sp;
+    const double qs = o.q2 * s;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+        const double phi = b * va[j] - vb[j] - sp * vg[j] + cst - qs * kap[j] * vs[j];
+        hrow[j] += wrow * vv[j] * phi;
+    }
+    wave_lds_sync();
+    // kappa_ii = 1 - k_ii = 1 (a valid set has a zero diagonal)
+    const double pd = b * al - be - sp * ga + cst - qs * 1.0 * s;
+    hdiag += wrow * v * pd;
+    fl += Cost<NC>::derivs;
+}
+
+// Cholesky factor of H + shift I, H = M + diag(dadd) with M given by rows
+// (hrow) and dadd this lane's diagonal addend: row gi of L in lrow (entries
+// past the diagonal are not meaningful), the whole factor in the group's LDS
+// (lower triangle and diagonal), 1/L_ii of this row in dinv.  Returns
+// whether every pivot was positive (the same in every lane).  As cholesky.
+template <int NC, int G>
+__device__ __forceinline__ bool chol_g(double (&lrow)[NC], double &dinv,
+                                       const double (&hrow)[NC], double dadd, double shift,
+                                       const Grp<NC, G> &g, uint32_t &fl)
+{
+    double *Ls = g.lsh();
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+        double s = hrow[j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) s -= lrow[k] * Ls[j * NC + k];
+        // lane j's s is the pivot (before its diagonal terms)
+        const double piv = gbcast(s + dadd, g.base, j) + shift;
+        ok = ok && (piv > 0.0);
+        const double d = sqrt(fmax(piv, 1e-300));
+        const double dj = 1.0 / d;
+        lrow[j] = s * dj;
+        Ls[g.row * NC + j] = lrow[j];
+        Ls[j * NC + j] = d;
+        wave_lds_sync();
+    }
+    dinv = 1.0 / Ls[g.row * NC + (g.act ? g.gi : 0)];
+    fl += Cost<NC>::chol;
+    return ok;
+}
+
+// y = L^-1 b (forward substitution; this lane's entries of b and y).
+template <int NC, int G>
+__device__ __forceinline__ double lower_solve_g(const double (&lrow)[NC], double dinv, double b,
+                                                const Grp<NC, G> &g)
+{
+    double *yv = g.vec(1);
+    double r = b;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+        const double yj = gbcast(r * dinv, g.base, j);
+        yv[j] = yj;
+        r -= lrow[j] * yj;   // used by the lanes past j only
+    }
+    wave_lds_sync();
+    const double y = yv[g.act ? g.gi : 0];
+    wave_lds_sync();
+    return g.act ? y : 0.0;
+}
+
+// x = L^-T y (back substitution, columns of L read from the LDS factor).
+template <int NC, int G>
+__device__ __forceinline__ double upper_solve_g(double dinv, double y, const Grp<NC, G> &g)
+{
+    const double *Ls = g.lsh();
+    double *xv = g.vec(2);
+    const int col = g.act ? g.gi : 0;
+    double r = y;
+#pragma unroll
+    for (int k = NC - 1; k >= 0; --k) {
+        const double xk = gbcast(r * dinv, g.base, k);
+        xv[k] = xk;
+        r -= Ls[k * NC + col] * xk;   // used by the lanes before k only
+    }
+    wave_lds_sync();
+    const double x = xv[col];
+    wave_lds_sync();
+    return g.act ? x : 0.0;
+}
+
+// (H v)_i = sum_j M_ij v_j + dadd_i v_i from this lane's row and the group's v.
+template <int NC, int G>
+__device__ __forceinline__ double hv_g(const double (&hrow)[NC], double dadd, double v,
+                                       const Grp<NC, G> &g)
+{
+    double *vv = g.vec(0);
+    vv[g.gi] = v;
+    wave_lds_sync();
+    double r = 0.0;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) r += hrow[j] * vv[j];
+    wave_lds_sync();
+    return r + dadd * v;
+}
+
+// Trust-region step of Hebden type across the group: as trust_step, with
+// this lane's entries of u and g, row of M and diagonal term (H = M +
+// diag(dadd), M_ii = hdiag); lrow/dinv hold this lane's row of the last
+// factor, the LDS the whole factor.
+template <int NC, int G>
+__device__ __forceinline__ double trust_step_g(double &u, double &radius, bool &eta0,
+                                               double (&lrow)[NC], double &dinv,
+                                               const double (&hrow)[NC], double hdiag,
+                                               double dadd, double gv, const Grp<NC, G> &g,
+                                               uint32_t &fl)
+{
+    const double mg = -gv;
+    eta0 = false;
+    bool have = false;
+    double eta1 = -1.0;
+    u = 0.0;
+    if (chol_g<NC, G>(lrow, dinv, hrow, dadd, 0.0, g, fl)) {
+        const double y = lower_solve_g<NC, G>(lrow, dinv, mg, g);
+        u = upper_solve_g<NC, G>(dinv, y, g);
+        fl += Cost<NC>::trisolve;
+        const double nu = sqrt(gsum<G>(u * u));
+        if (!(radius > 0.0)) radius = nu;
+        if (nu <= radius) {
+            eta0 = true;
+            have = true;
+        } else {
+            const double q = lower_solve_g<NC, G>(lrow, dinv, u, g);
+            const double nq = sqrt(gsum<G>(q * q));
+            eta1 = (nu / nq) * (nu / nq) * (nu - radius) / radius;
+            fl += NC * NC + 2 * NC + 6;
+        }
+    } else if (!(radius > 0.0)) {
+        radius = 1.0;
+    }
+    if (!have) {
+        double rs = 0.0;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) rs += fabs(hrow[j]);
+        rs += fabs(hdiag + dadd) - fabs(hdiag);
+        const double hmin = gmin<G>(g.act ? hdiag + dadd : INFINITY);
+        const double rowmax = gmax<G>(g.act ? rs : 0.0);
+        double elo = fmax(0.0, -hmin);
+        double ehi = sqrt(gsum<G>(gv * gv)) / radius + rowmax;
+        double eta = elo > 0.0 ? elo : 1e-3 * ehi;
+        if (eta1 > 0.0 && eta1 < ehi) eta = eta1;
+        for (int it = 0; it < 12; ++it) {
+            if (!chol_g<NC, G>(lrow, dinv, hrow, dadd, eta, g, fl)) {
+                elo = eta;
+                eta = fmax(sqrt(elo * ehi), elo + 1e-3 * (ehi - elo));
+                continue;
+            }
+            const double y = lower_solve_g<NC, G>(lrow, dinv, mg, g);
+            const double ut = upper_solve_g<NC, G>(dinv, y, g);
+            fl += Cost<NC>::trisolve;
+            const double nu = sqrt(gsum<G>(ut * ut));
+            u = ut;
+            have = true;
+            if (nu > 0.9 * radius && nu < 1.1 * radius) break;
+            if (nu > radius) elo = eta; else ehi = eta;
+            const double q = lower_solve_g<NC, G>(lrow, dinv, ut, g);
+            const double nq = sqrt(gsum<G>(q * q));
+            double en = eta + (nu / nq) * (nu / nq) * (nu - radius) / radius;
+            if (!(en > elo && en < ehi)) en = fmax(sqrt(elo * ehi), elo + 1e-3 * (ehi - elo));
+            eta = en;
+        }
+        if (!have) {
+            const double hg = hv_g<NC, G>(hrow, dadd, gv, g);
+            const double gg = gsum<G>(gv * gv);
+            const double ghg = gsum<G>(gv * hg);
+            const double tmax = radius / sqrt(gg);
+            const double t = (ghg > 0.0) ? fmin(gg / ghg, tmax) : tmax;
+            u = -t * gv;
+            fl += 2 * NC * NC + 4 * NC;
+        }
+    }
+    const double hu = hv_g<NC, G>(hrow, dadd, u, g);
+    const double gu = gsum<G>(gv * u);
+    const double uhu = gsum<G>(u * hu);
+    fl += 2 * NC * NC + 2 * NC;
+    return gu + 0.5 * uhu;
+}
+
+// Row gi of the k table as kappa_ij = 1 - k_ij (kappa_ii = 1: a valid set has
+// a zero diagonal; the lanes beyond nc read row 0 and contribute nothing).
+template <int NC, bool PM, int G>
+__device__ __forceinline__ void load_kappa(double (&kap)[NC], const Ctx<NC> &c, int64_t m,
+                                           const Grp<NC, G> &g)
+{
+    const Props pp = mix_props<NC, PM>(c.pr, m);
+    const int row = g.act ? g.gi : 0;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) kap[j] = 1.0 - pp.K[row * NC + j];
+}
+
+// ---------------------------------------------------------------------------
+// SaTr with one group per trial (as SaTrItem)
+// ---------------------------------------------------------------------------
+template <int NC, bool PM, int G>
+struct SaTrGroup {
+    static constexpr int WAVES = 2;   // minimum wavefronts per SIMD
+    static constexpr uint32_t OUT = 0u;
+    static constexpr int LIST = L_SATR;
+    static constexpr int LIST2 = -1;
+    int64_t m;
+    int t;
+    double lw, lacc, d, s, b;   // this lane's component
+    double rad, facc, pred, gacc, zw;
+    bool pend;
+    int tr, steps;
+    uint32_t fl, st;
+
+    __device__ __forceinline__ bool begin(const Ctx<NC> &c, uint32_t id, const Grp<NC, G> &g)
+    {
+        m = id >> 1;
+        t = (int)(id & 1u);
+        const MixRec<NC> &r = c.rec[m];
+        const int i = g.act ? g.gi : 0;
+        s = g.act ? r.s[i] : 0.0;
+        b = g.act ? r.b[i] : 0.0;
+        d = g.act ? r.d[i] : 0.0;
+        lw = g.act ? r.lw[t][i] : 0.0;
+        fl = r.tfl[t];
+        st = r.tst[t];
+        rad = 0.0;
+        pend = false;
+        tr = 0;
+        steps = 0;
+        zw = -1.0;
+        return true;
+    }
+
+    __device__ __forceinline__ void done(const Ctx<NC> &c, double tm, const Grp<NC, G> &g)
+    {
+        MixRec<NC> &r = c.rec[m];
+        if (g.act) r.lw[t][g.gi] = lw;
+        if (g.gi == 0) {
+            r.tm[t] = tm;
+            r.it[t == 0 ? 2 : 4] = (int16_t)tr;
+            r.tfl[t] = fl;
+            r.tst[t] = st;
+        }
+    }
+
+    __device__ __forceinline__ bool step(const Ctx<NC> &c, const Grp<NC, G> &g)
+    {
+        const FlashArgs &a = c.a;
+        double kap[NC];
+        load_kappa<NC, PM, G>(kap, c, m, g);
+        const double W = g.act ? exp(lw) : 0.0;
+        fl += NC;
+        PhaseG o;
+        phase_eval_g<NC, G>(o, g, s, b, kap, W, fl, zw);
+        zw = o.Z;
+        const double grad = g.act ? lw + o.lnphi - d : 0.0;
+        const double tm = 1.0 + gsum<G>(W * (grad - 1.0));
+        const double sw = gsum<G>(W);
+        const double gv = sqrt(W) * grad;
+        const double gmx = gmax<G>(fabs(gv));
+        fl += 9 * NC;
+        if (pend) {
+            pend = false;
+            bool accept;
+            double ratio = 1.0;
+            if (fabs(pred) < 1e-13) {
+                accept = gmx < gacc;
+            } else {
+                ratio = (tm - facc) / pred;
+                accept = (tm < facc) && ratio > 0.0;
+            }
+            if (!accept) {
+                rad *= 0.5;
+                lw = lacc;
+                if (++steps < kStepGuard) return false;   // re-evaluate there
+                st |= kStSaUnconv;
+                done(c, facc, g);
+                return true;
+            }
+            if (ratio <= 0.25) rad *= 0.5;
+            else if (ratio >= 0.75) rad *= 2.0;
+        }
+        if (tm < -a.eps_tm || gmx < a.tol_sa_tr) {
+            done(c, tm, g);
+            return true;
+        }
+        if (tr >= a.max_tr_sa || ++steps >= kStepGuard) {
+            st |= kStSaUnconv;
+            done(c, tm, g);
+            return true;
+        }
+        // H_ij = delta_ij (1 + grad_i/2) + sqrt(c_i c_j) Phi_ij
+        const double rc = sqrt(W / sw);
+        double hrow[NC], hdiag = 0.0;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) hrow[j] = 0.0;
+        phase_derivs_g<NC, G>(hrow, hdiag, o, g, s, b, kap, rc, rc, fl);
+        const double dadd = 1.0 + 0.5 * grad;
+        fl += 2 * Tri<NC>::N + 4 * NC;
+        double lrow[NC], dinv = 0.0, u;
+        bool eta0;
+        double pr = trust_step_g<NC, G>(u, rad, eta0, lrow, dinv, hrow, hdiag, dadd, gv, g, fl);
+        const double bi = 2.0 * sqrt(W);
+        const double amax = gmin<G>((g.act && u < 0.0) ? fmin(1.0, 0.99 * bi / -u) : 1.0);
+        if (amax < 1.0) {
+            const double gu = gsum<G>(gv * u);
+            pr = amax * gu + amax * amax * (pr - gu);
+        }
+        lacc = lw;
+        if (g.act) lw = 2.0 * log(sqrt(W) + 0.5 * amax * u);
+        fl += 6 * NC;
+        facc = tm;
+        gacc = gmx;
+        pred = pr;
+        pend = true;
+        ++tr;
+        return false;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// SpNt with one group per split (as SpNtItem)
+// ---------------------------------------------------------------------------
+template <int NC, bool PM, int G>
+struct SpNtGroup {
+    static constexpr int WAVES = 2;   // minimum wavefronts per SIMD
+    static constexpr uint32_t OUT = 0u;
+    static constexpr int LIST = L_NT;
+    static constexpr int LIST2 = L_NTP;
+    static constexpr int NP = Tri<NC>::N;
+    int64_t m;
+    double z, v0, v1, s, b;   // this lane's component
+    double srad, sfacc, spred, sgacc, sdprev, zx, zy;
+    bool spend, spol;
+    int tr, pol, steps;
+    uint32_t fl, status;
+
+    __device__ __forceinline__ bool begin(const Ctx<NC> &c, uint32_t id, const Grp<NC, G> &g)
+    {
+        m = id;
+        const MixRec<NC> &r = c.rec[m];
+        const int i = g.act ? g.gi : 0;
+        // the feed normalised with the sum taken in component order, as load_z
+        double sz = 0.0;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) sz += c.a.z[m * NC + j];
+        z = g.act ? c.a.z[m * NC + i] / sz : 0.0;
+        s = g.act ? r.s[i] : 0.0;
+        b = g.act ? r.b[i] : 0.0;
+        v0 = g.act ? r.lk[i] : 0.0;
+        v1 = v0;
+        fl = r.fl;
+        status = r.status;
+        srad = 0.0;
+        spend = spol = false;
+        tr = pol = steps = 0;
+        zx = zy = -1.0;
+        return true;
+    }
+
+    // this lane's x_i, y_i from n^V: y = n^V/sum n^V, x = (z - n^V)/sum(z - n^V)
+    __device__ __forceinline__ void xy_from_nv(double &x, double &y, double &bv)
+    {
+        const double xl = z - v0;
+        const double sv = gsum<G>(v0), sl = gsum<G>(xl);
+        x = xl * (1.0 / sl);
+        y = v0 * (1.0 / sv);
+        bv = sv;
+        fl += 5 * NC + 2;
+    }
+
+    __device__ __forceinline__ void write_single(const Ctx<NC> &c, const Grp<NC, G> &g,
+                                                 uint32_t bits, const int16_t (&it)[8])
+    {
+        const FlashArgs &a = c.a;
+        if (g.act) {
+            a.x[m * NC + g.gi] = z;
+            a.y[m * NC + g.gi] = z;
+        }
+        if (g.gi == 0) {
+            a.label[m] = 0;
+            a.beta[m] = -1.0;
+            if (a.iters) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) a.iters[m * 8 + k] = it[k];
+            }
+            if (a.status) a.status[m] = (uint16_t)bits;
+            if (a.flops) a.flops[m] = fl;
+        }
+    }
+
+    // savef: the group's LDS holds the factor of H' at the solution
+    __device__ __forceinline__ void finish(const Ctx<NC> &c, const Grp<NC, G> &g, double zx_,
+                                           double zy_, bool savef, double vs)
+    {
+        const FlashArgs &a = c.a;
+        const MixRec<NC> &r = c.rec[m];
+        int16_t it[8];
+        load_it<NC>(it, r);
+        it[6] = (int16_t)tr;
+        it[7] = (int16_t)pol;
+        double x, y, bv;
+        xy_from_nv(x, y, bv);
+        const double lk = gmax<G>(g.act ? fabs(log(y / x)) : 0.0);
+        if (!(bv > kMinPhase && bv < 1.0 - kMinPhase)) {
+            write_single(c, g, status | kStSplitFailed, it);
+            return;
+        }
+        if (lk < 1e-6) {
+            write_single(c, g, status | kStSplitTrivial, it);
+            return;
+        }
+        const bool swap = zx_ > zy_;
+        if (swap) status |= kStSwapped;
+        if (g.act) {
+            a.x[m * NC + g.gi] = swap ? y : x;
+            a.y[m * NC + g.gi] = swap ? x : y;
+            if (a.keep_factor && a.factor) {
+                // factor of H~ = D^(1/2) H' D^(1/2): row i of L' scaled by 1/v_i
+                const int i = g.gi;
+                const double *Ls = g.lsh();
+                for (int j = 0; j <= i; ++j)
+                    a.factor[m * NP + i * (i + 1) / 2 + j] = savef ? Ls[i * NC + j] / vs : NAN;
+            }
+        }
+        if (g.gi == 0) {
+            a.label[m] = 1;
+            a.beta[m] = swap ? 1.0 - bv : bv;
+            if (a.iters) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) a.iters[m * 8 + k] = it[k];
+            }
+            if (a.status) a.status[m] = (uint16_t)status;
+            if (a.flops) a.flops[m] = fl;
+        }
+    }
+
+    __device__ __forceinline__ bool step(const Ctx<NC> &c, const Grp<NC, G> &g)
+    {
+        const FlashArgs &a = c.a;
+        double kap[NC];
+        load_kappa<NC, PM, G>(kap, c, m, g);
+        double w0, w1, bvap;
+        xy_from_nv(w0, w1, bvap);
+        // scaled Hessian H' = (I - v v' + V((1-th) Phi^V + th Phi^L)V)/(th(1-th)),
+        // v_i = sqrt(x_i y_i / z_i)
+        const double vs = g.act ? sqrt(w0 * w1 / z) : 0.0;
+        fl += 4 * NC;
+        double hrow[NC], lrow[NC], hdiag = 0.0, dinv = 0.0;
+#pragma unroll
+        for (int j = 0; j < NC; ++j) { hrow[j] = 0.0; lrow[j] = 0.0; }
+        PhaseG o;
+        phase_eval_g<NC, G>(o, g, s, b, kap, w0, fl, zx);
+        zx = o.Z;
+        const double th = bvap;
+        phase_derivs_g<NC, G>(hrow, hdiag, o, g, s, b, kap, th * vs, vs, fl);
+        fl += 3 * NP;
+        const double r0 = o.lnphi;
+        const double Z0 = o.Z;
+        phase_eval_g<NC, G>(o, g, s, b, kap, w1, fl, zy);
+        zy = o.Z;
+        phase_derivs_g<NC, G>(hrow, hdiag, o, g, s, b, kap, (1.0 - th) * vs, vs, fl);
+        // gradient of G over n^V (eq. split_grad) and G itself (eq. gibbs)
+        const double fx = g.act ? log(w0) + r0 : 0.0;
+        const double fy = g.act ? log(w1) + o.lnphi : 0.0;
+        const double gt = fy - fx;
+        const double G_ = gsum<G>((z - v0) * fx + v0 * fy);
+        const double gmx = gmax<G>(fabs(gt));
+        const double gs = vs * gt;
+        fl += 11 * NC;
+        const double sc = 1.0 / (th * (1.0 - th));
+        {
+            double *vv = g.vec(0);
+            vv[g.gi] = vs;
+            wave_lds_sync();
+#pragma unroll
+            for (int j = 0; j < NC; ++j) hrow[j] = g.act ? (hrow[j] - vs * vv[j]) * sc : 0.0;
+            wave_lds_sync();
+        }
+        // the identity term of H' is the diagonal addend sc
+        hdiag = g.act ? (hdiag - vs * vs) * sc : 0.0;
+        const double dadd = sc;
+        fl += 8 * NP;
+        if (spend) {
+            spend = false;
+            bool accept;
+            double ratio = 1.0;
+            if (fabs(spred) < 1e-13) {
+                accept = gmx < sgacc;
+            } else {
+                ratio = (G_ - sfacc) / spred;
+                accept = (G_ < sfacc) && ratio > 0.0;
+            }
+            if (!accept) {
+                srad *= 0.5;
+                v0 = v1;
+                if (++steps < kStepGuard) return false;   // re-evaluate there
+                status |= kStSplitUnconv | kStStepCap;
+                finish(c, g, Z0, o.Z, false, vs);
+                return true;
+            }
+            if (ratio <= 0.25) srad *= 0.5;
+            else if (ratio >= 0.75) srad *= 2.0;
+        }
+        if (!spol && gmx < a.tol_split_tr) {
+            spol = true;   // the paper's criterion holds: refine
+            sdprev = 1e300;
+        }
+        double u;
+        bool eta0;
+        if (spol) {
+            // Newton refinement while H is positive definite; an indefinite H
+            // sends the split back to the trust region
+            double rad = 1e300;
+            trust_step_g<NC, G>(u, rad, eta0, lrow, dinv, hrow, hdiag, dadd, gs, g, fl);
+            if (!eta0) spol = false;
+        }
+        if (spol) {
+            u *= vs;
+            double lim = 1.0;
+            if (g.act && u < 0.0) lim = fmin(lim, 0.99 * v0 / -u);
+            if (g.act && u > 0.0) lim = fmin(lim, 0.99 * (z - v0) / u);
+            const double dmax = gmax<G>(fabs(u));
+            const double amax = gmin<G>(lim);
+            v0 += amax * u;
+            fl += 6 * NC;
+            const bool conv = dmax < a.tol_polish || (dmax < 1e-10 && dmax >= 0.5 * sdprev);
+            if (conv || pol >= a.max_polish || ++steps >= kStepGuard) {
+                if (!conv && !(dmax < 1e-10)) status |= kStSplitUnconv;
+                finish(c, g, Z0, o.Z, true, vs);
+                return true;
+            }
+            sdprev = dmax;
+            ++pol;
+            return false;
+        }
+        if (tr >= a.max_tr_split || ++steps >= kStepGuard) {
+            status |= kStSplitUnconv;
+            finish(c, g, Z0, o.Z, false, vs);
+            return true;
+        }
+        status |= kStSplitTr;
+        double pr = trust_step_g<NC, G>(u, srad, eta0, lrow, dinv, hrow, hdiag, dadd, gs, g, fl);
+        // dn = v o u, kept inside 0 < n^V < z
+        u *= vs;
+        double lim = 1.0;
+        if (g.act && u < 0.0) lim = fmin(lim, 0.99 * v0 / -u);
+        if (g.act && u > 0.0) lim = fmin(lim, 0.99 * (z - v0) / u);
+        const double amax = gmin<G>(lim);
+        if (amax < 1.0) {
+            const double gu = gsum<G>(gt * u);
+            pr = amax * gu + amax * amax * (pr - gu);
+        }
+        v1 = v0;
+        v0 += amax * u;
+        fl += 6 * NC;
+        sfacc = G_;
+        sgacc = gmx;
+        spred = pr;
+        spend = true;
+        ++tr;
+        return false;
+    }
+};
+
+}  // namespace ptf

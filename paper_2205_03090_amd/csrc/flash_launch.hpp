@@ -19,7 +19,9 @@
 
 #include "flash_api.hpp"
 #include "flash_stages.hpp"
+#include "flash_group.hpp"
 #include "adjoint_device.hpp"
+#include "tuned_gfx950.hpp"
 
 namespace ptf {
 namespace {
@@ -36,13 +38,24 @@ __global__ void reset_counters(unsigned long long *q, int n)
 template <class Item, int NC>
 __device__ __forceinline__ int64_t stage_count(const Ctx<NC> &c)
 {
-    return Item::LIST < 0 ? c.a.n : (int64_t)c.L.count[Item::LIST];
+    if (Item::LIST < 0) return c.a.n;
+    int64_t k = (int64_t)c.L.count[Item::LIST];
+    if (Item::LIST2 >= 0) k += (int64_t)c.L.count[Item::LIST2 < 0 ? 0 : Item::LIST2];
+    return k;
 }
 
+// Id of input entry k: entries of LIST first, then those of LIST2.
 template <class Item, int NC>
 __device__ __forceinline__ uint32_t stage_id(const Ctx<NC> &c, int64_t k)
 {
-    return Item::LIST < 0 ? (uint32_t)k : c.L.ids[Item::LIST < 0 ? 0 : Item::LIST][k];
+    if (Item::LIST < 0) return (uint32_t)k;
+    constexpr int l1 = Item::LIST < 0 ? 0 : Item::LIST;
+    if (Item::LIST2 >= 0) {
+        constexpr int l2 = Item::LIST2 < 0 ? 0 : Item::LIST2;
+        const int64_t n1 = (int64_t)c.L.count[l1];
+        if (k >= n1) return c.L.ids[l2][k - n1];
+    }
+    return c.L.ids[l1][k];
 }
 
 // Ids a wavefront claims from a stage's input with one atomic (after its
@@ -209,6 +222,66 @@ stage_persistent(Ctx<NC> c, const double *__restrict__ Tc, const double *__restr
             const int q = slot_of<OUT>(l);
             if (fill[q] > 0) flush_list(c.L, l, buf[q], fill[q], lane);
         }
+    }
+}
+
+// Persistent stage with one group of G lanes per item (flash_group.hpp): as
+// stage_persistent, with groups in place of lanes.  The lowest lane of each
+// group takes part in the claim; the items of these stages append to no
+// list.
+template <class Item, int NC, int G>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Item::WAVES)))
+stage_persistent_group(Ctx<NC> c, const double *__restrict__ Tc, const double *__restrict__ Pc,
+                       const double *__restrict__ om, const double *__restrict__ K,
+                       unsigned long long *__restrict__ take)
+{
+    static_assert(Item::OUT == 0u, "group items append to no list");
+    static_assert(64 % G == 0 && G >= NC, "a group spans the components within one wavefront");
+    __shared__ double group_lds[kBlock / G][GroupLds<NC, G>::N];
+    c.pr = Props{Tc, Pc, om, K};
+    const int64_t count = stage_count<Item, NC>(c);
+    const int lane = (int)__lane_id();
+    Grp<NC, G> g;
+    g.gi = lane % G;
+    g.base = lane - g.gi;
+    g.act = g.gi < NC;
+    g.row = g.act ? g.gi : NC;
+    g.sh = group_lds[threadIdx.x / G];
+    const unsigned long long nw = (unsigned long long)gridDim.x * (blockDim.x / 64);
+    const unsigned long long wid =
+        (unsigned long long)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    const unsigned long long s0 = (unsigned long long)(count > 0 ? count : 0) * 3ull / 4ull / nw;
+    const unsigned long long dyn0 = nw * s0;
+    unsigned long long cb = wid * s0, ce = cb + s0;   // claimed, not yet taken: [cb, ce)
+    Item it;
+    bool live = false, gone = false;   // the same in every lane of a group
+    for (;;) {
+        const bool want = !live && !gone;
+        const unsigned long long mask = __ballot(want && g.gi == 0);
+        if (mask) {
+            const int r = __popcll(mask);
+            const unsigned long long avail = ce - cb;
+            unsigned long long nb = 0;
+            if (avail < (unsigned long long)r) {
+                if (lane == 0) nb = dyn0 + atomicAdd(take, (unsigned long long)kChunk);
+                nb = bcast64(nb, 0);
+            }
+            if (want) {
+                const unsigned long long rank =
+                    (unsigned long long)__popcll(mask & lanes_below(g.base));
+                const unsigned long long k = rank < avail ? cb + rank : nb + (rank - avail);
+                if ((int64_t)k < count) live = it.begin(c, stage_id<Item, NC>(c, (int64_t)k), g);
+                else gone = true;
+            }
+            if (avail < (unsigned long long)r) {
+                cb = nb + ((unsigned long long)r - avail);
+                ce = nb + kChunk;
+            } else {
+                cb += (unsigned long long)r;
+            }
+        }
+        if (__ballot(!gone) == 0ull) break;
+        if (live) live = !it.step(c, g);
     }
 }
 
@@ -459,7 +532,7 @@ size_t workspace_bytes(int64_t n, int form)
 {
     const size_t un = (size_t)n;
     size_t b = 256 + align256(un * sizeof(MixRec<NC>)) + 3 * align256(2 * un * 4) +
-               3 * align256(un * 4);
+               4 * align256(un * 4);
     if (form == PTFLASH_FORM_PLAIN)
         b += align256(2 * un * plain_state_bytes<NC>()) + 2 * align256(2 * un * 4);
     return b;
@@ -490,6 +563,7 @@ void setup_ctx(Ctx<NC> &c, const FlashArgs &a, int64_t n, void *ws, char **tail)
     c.L.ids[L_SAFIN] = cv.take<uint32_t>((size_t)n * 4);
     c.L.ids[L_SPLIT] = cv.take<uint32_t>((size_t)n * 4);
     c.L.ids[L_NT] = cv.take<uint32_t>((size_t)n * 4);
+    c.L.ids[L_NTP] = cv.take<uint32_t>((size_t)n * 4);
     c.L.count = cnt;
     *tail = cv.p;
 }
@@ -509,7 +583,7 @@ template <class Item, int NC>
 int run_persistent_stage(const Ctx<NC> &c, const ptflash_problem *p,
                                 const ptflash_options *o, int take_slot, hipStream_t s)
 {
-    const int block = o->block > 0 ? o->block : kBlock;
+    const int block = o->block > 0 ? o->block : tuned_block(NC);
     if (block % 64 != 0 || block > kBlock) return PTFLASH_EINVAL;
     const int grid = grid_for((const void *)stage_persistent<Item, NC>, block, o->grid);
     if (grid <= 0) return PTFLASH_EHIP;
@@ -518,10 +592,56 @@ int run_persistent_stage(const Ctx<NC> &c, const ptflash_problem *p,
     return hipGetLastError() == hipSuccess ? PTFLASH_OK : PTFLASH_EHIP;
 }
 
+template <class Item, int NC, int G>
+int run_persistent_stage_group(const Ctx<NC> &c, const ptflash_problem *p,
+                               const ptflash_options *o, int take_slot, hipStream_t s)
+{
+    const int block = o->block > 0 ? o->block : tuned_block(NC);
+    if (block % 64 != 0 || block > kBlock) return PTFLASH_EINVAL;
+    const int grid = grid_for((const void *)stage_persistent_group<Item, NC, G>, block, o->grid);
+    if (grid <= 0) return PTFLASH_EHIP;
+    hipLaunchKernelGGL((stage_persistent_group<Item, NC, G>), dim3(grid), dim3(block), 0, s, c,
+                       p->Tc, p->Pc, p->omega, p->kij, c.L.count + take_slot);
+    return hipGetLastError() == hipSuccess ? PTFLASH_OK : PTFLASH_EHIP;
+}
+
+// Lanes per mixture of the trust-region stages: the option, or the tuned
+// choice for this nc; 0 when the value is not available for this nc.
+template <int NC>
+int lanes_for(const ptflash_options *o)
+{
+    const int l = o->lanes_per_mixture > 0 ? o->lanes_per_mixture : tuned_lanes(NC);
+    if (l == 1) return 1;
+    if (NC < kGroupMinNc) return 0;
+    if (l == 16 && NC <= 16) return 16;
+    if (l == 32 && NC <= 32) return 32;
+    return 0;
+}
+
+// One trust-region stage (Item1: one mixture per lane; ItemG<G>: groups).
+template <template <int, bool> class Item1, template <int, bool, int> class ItemG, int NC,
+          bool PM>
+int run_tr_stage(const Ctx<NC> &c, const ptflash_problem *p, const ptflash_options *o,
+                 int lanes, int take_slot, hipStream_t s)
+{
+    if constexpr (NC >= kGroupMinNc && NC <= 16) {
+        if (lanes == 16)
+            return run_persistent_stage_group<ItemG<NC, PM, 16>, NC, 16>(c, p, o, take_slot, s);
+    }
+    if constexpr (NC >= kGroupMinNc && NC <= 32) {
+        if (lanes == 32)
+            return run_persistent_stage_group<ItemG<NC, PM, 32>, NC, 32>(c, p, o, take_slot, s);
+    }
+    if (lanes == 1) return run_persistent_stage<Item1<NC, PM>, NC>(c, p, o, take_slot, s);
+    return PTFLASH_EINVAL;
+}
+
 template <int NC, bool PM>
 int launch_persistent(const FlashArgs &a, const ptflash_problem *p, const ptflash_options *o,
                       void *ws, hipStream_t s)
 {
+    const int lanes = lanes_for<NC>(o);
+    if (lanes == 0) return PTFLASH_EINVAL;
     Ctx<NC> c;
     char *tail;
     setup_ctx<NC>(c, a, p->n, ws, &tail);
@@ -530,10 +650,10 @@ int launch_persistent(const FlashArgs &a, const ptflash_problem *p, const ptflas
     if ((rc = run_persistent_stage<FeedItem<NC, PM>, NC>(c, p, o, kTake0 + 0, s))) return rc;
     if ((rc = run_persistent_stage<PreSsItem<NC, PM>, NC>(c, p, o, kTake0 + 1, s))) return rc;
     if ((rc = run_persistent_stage<SaSsItem<NC, PM>, NC>(c, p, o, kTake0 + 2, s))) return rc;
-    if ((rc = run_persistent_stage<SaTrItem<NC, PM>, NC>(c, p, o, kTake0 + 3, s))) return rc;
+    if ((rc = run_tr_stage<SaTrItem, SaTrGroup, NC, PM>(c, p, o, lanes, kTake0 + 3, s))) return rc;
     if ((rc = run_persistent_stage<SaFinItem<NC, PM>, NC>(c, p, o, kTake0 + 4, s))) return rc;
     if ((rc = run_persistent_stage<SpSsItem<NC, PM>, NC>(c, p, o, kTake0 + 5, s))) return rc;
-    if ((rc = run_persistent_stage<SpNtItem<NC, PM>, NC>(c, p, o, kTake0 + 6, s))) return rc;
+    if ((rc = run_tr_stage<SpNtItem, SpNtGroup, NC, PM>(c, p, o, lanes, kTake0 + 6, s))) return rc;
     return PTFLASH_OK;
 }
 
@@ -561,6 +681,11 @@ int run_plain_stage(const Ctx<NC> &c, const ptflash_problem *p, char *tail, hipS
     int64_t count = n;
     int rc;
     if (Item::LIST >= 0 && (rc = read_count(c.L.count + Item::LIST, count, s))) return rc;
+    if (Item::LIST2 >= 0) {
+        int64_t c2 = 0;
+        if ((rc = read_count(c.L.count + (Item::LIST2 < 0 ? 0 : Item::LIST2), c2, s))) return rc;
+        count += c2;
+    }
     if (count == 0) return PTFLASH_OK;
     auto grid = [](int64_t k) { return dim3((unsigned)((k + kBlock - 1) / kBlock)); };
     hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, na, 1);

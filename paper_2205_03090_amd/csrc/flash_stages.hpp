@@ -79,7 +79,12 @@ struct MixRec {
 
 
 // Work lists: ids (mixture m, or trial 2m + t) and their counts.
-enum ListId : int { L_SA = 0, L_SATR = 1, L_SAFIN = 2, L_SPLIT = 3, L_NT = 4, L_PRE = 5, L_COUNT = 6 };
+// L_NT holds the splits that need the trust region, L_NTP those that only
+// need the refinement; the last stage reads L_NT, then L_NTP, so that the
+// long trust-region runs start first and the short refinements fill the end.
+enum ListId : int {
+    L_SA = 0, L_SATR = 1, L_SAFIN = 2, L_SPLIT = 3, L_NT = 4, L_PRE = 5, L_NTP = 6, L_COUNT = 7
+};
 
 struct Lists {
     uint32_t *ids[L_COUNT];
@@ -291,6 +296,7 @@ struct FeedItem {
     static constexpr uint32_t OUT = (1u << L_SA) | (1u << L_SAFIN) | (1u << L_PRE);   // lists the steps append to
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = -1;   // input: mixtures 0..n-1
+    static constexpr int LIST2 = -1;   // second input list, read after LIST
     int64_t m;
     double T, P;
     double z[NC];
@@ -375,6 +381,7 @@ struct PreSsItem {
     static constexpr uint32_t OUT = (1u << L_SA) | (1u << L_SAFIN) | (1u << L_SPLIT);   // lists the steps append to
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_PRE;
+    static constexpr int LIST2 = -1;   // second input list, read after LIST
     int64_t m;
     double z[NC], d[NC], lk[NC];
     Eos<NC> e;
@@ -453,6 +460,7 @@ struct SaSsItem {
     static constexpr uint32_t OUT = 1u << L_SATR;   // lists the steps append to
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_SA;
+    static constexpr int LIST2 = -1;   // second input list, read after LIST
     int64_t m;
     int t;
     double lw[NC], prev[NC], d[NC];
@@ -556,6 +564,7 @@ struct SaTrItem {
     static constexpr uint32_t OUT = 0u;   // lists the steps append to
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_SATR;
+    static constexpr int LIST2 = -1;   // second input list, read after LIST
     static constexpr int NP = Tri<NC>::N;
     int64_t m;
     int t;
@@ -703,6 +712,7 @@ struct SaFinItem {
     static constexpr uint32_t OUT = 1u << L_SPLIT;   // lists the steps append to
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_SAFIN;
+    static constexpr int LIST2 = -1;   // second input list, read after LIST
     int64_t m;
 
     __device__ __forceinline__ bool begin(const Ctx<NC> &c, uint32_t id)
@@ -747,9 +757,10 @@ struct SaFinItem {
 template <int NC, bool PM>
 struct SpSsItem {
     static constexpr int WAVES = (NC <= 8 ? 2 : 1);   // minimum wavefronts per SIMD
-    static constexpr uint32_t OUT = 1u << L_NT;   // lists the steps append to
+    static constexpr uint32_t OUT = (1u << L_NT) | (1u << L_NTP);   // lists the steps append to
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_SPLIT;
+    static constexpr int LIST2 = -1;   // second input list, read after LIST
     int64_t m;
     double z[NC], lk[NC], prev[NC];
     Eos<NC> e;
@@ -866,7 +877,7 @@ struct SpSsItem {
         r.it[5] = (int16_t)ss;
         r.fl = fl;
         r.status = status | (conv ? 0u : kStSplitTr);
-        ob.put(L_NT, (uint32_t)m);
+        ob.put(conv ? L_NTP : L_NT, (uint32_t)m);
         return true;
     }
 };
@@ -881,6 +892,7 @@ struct SpNtItem {
     static constexpr uint32_t OUT = 0u;   // lists the steps append to
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_NT;
+    static constexpr int LIST2 = L_NTP;   // refinement-only splits, read after L_NT
     static constexpr int NP = Tri<NC>::N;
     int64_t m;
     double z[NC], v0[NC], v1[NC];

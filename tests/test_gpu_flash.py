@@ -148,9 +148,10 @@ def test_per_mixture_component_sets(nc):
     rep = compare(g, _oracle(w), w=w)
     _report(f"pm{nc}", rep)
     _assert_parity(rep, path_agree=0.97)
+    g1 = _run(w, lanes_per_mixture=1)
     gp = _run(w, form=_capi.FORM_PLAIN)
     for k in ("label", "beta", "x", "y", "iters", "status"):
-        assert np.array_equal(g[k], gp[k], equal_nan=True), k
+        assert np.array_equal(g1[k], gp[k], equal_nan=True), k
 
 
 def test_invalid_inputs_flagged():
@@ -197,10 +198,11 @@ def _nc20_shared(n):
                                      (_nc20_shared, 3000)])
 def test_plain_form_bitwise_equal_to_persistent(maker, n):
     # the plain form (one launch per stage iteration, compaction, host count
-    # read, stage barriers) runs the same per-mixture arithmetic
+    # read, stage barriers) runs the same per-mixture arithmetic as the
+    # persistent form with one mixture per lane
     w = maker(n=n)
     print(f"case plain {w.name} n={n}", flush=True)
-    a = _run(w)
+    a = _run(w, lanes_per_mixture=1)
     b = _run(w, form=_capi.FORM_PLAIN)
     for k in ("label", "beta", "x", "y", "iters", "status", "flops"):
         assert np.array_equal(a[k], b[k], equal_nan=True), k
