@@ -124,6 +124,9 @@ typedef struct {
                               i; needs 8 <= nc <= lanes).  Other values, or a
                               group too small for nc: PTFLASH_EINVAL.  The
                               plain form always runs one mixture per lane. */
+    int32_t lanes_split;   /* the same choice for the split trust-region stage
+                              alone: 0 = the tuned choice when
+                              lanes_per_mixture is 0, else lanes_per_mixture */
 } ptflash_options;
 
 /* Outputs (device pointers).  label, beta, x, y are required; the others may

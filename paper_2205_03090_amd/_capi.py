@@ -44,7 +44,7 @@ class Options(C.Structure):
                 ("tol_split_tr", C.c_double), ("tol_polish", C.c_double),
                 ("eps_tm", C.c_double), ("form", C.c_int32), ("keep_factor", C.c_int32),
                 ("block", C.c_int32), ("grid", C.c_int32),
-                ("lanes_per_mixture", C.c_int32)]
+                ("lanes_per_mixture", C.c_int32), ("lanes_split", C.c_int32)]
 
 
 class Result(C.Structure):

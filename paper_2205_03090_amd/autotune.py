@@ -1,7 +1,7 @@
 """Chooses, per component count, the launch shape of the persistent flash on
-this GPU: the lanes per mixture of the trust-region stages (1, or a group of
-16 or 32 lanes) and the threads per block, by timing every candidate on a
-seeded sample workload.
+this GPU: the lanes per mixture of each of the two trust-region stages (1, or
+a group of 16 or 32 lanes) and the threads per block, by timing every
+candidate on a seeded sample workload.
 
   python -m paper_2205_03090_amd.autotune --out DIR [--n 200000] [--reps 3]
 
@@ -24,48 +24,62 @@ GROUP_MIN_NC = 8   # the group variants are compiled from this nc on
 BLOCKS = (64, 128, 256)
 
 
-def candidates(nc: int):
+def lane_choices(nc: int):
     lanes = [1]
     if nc >= GROUP_MIN_NC and nc <= 16:
         lanes.append(16)
     if nc >= GROUP_MIN_NC:
         lanes.append(32)
-    return [(l, b) for l in lanes for b in BLOCKS]
+    return lanes
 
 
-def time_one(args, lanes: int, block: int, reps: int) -> float:
+def candidates(nc: int):
+    """(stability lanes, split lanes, block) triples."""
+    ls = lane_choices(nc)
+    return [(a, b, k) for a in ls for b in ls for k in BLOCKS]
+
+
+def time_one(args, la: int, lb: int, block: int, reps: int) -> float:
     import torch
     from . import api
-    out = api.flash(*args, lanes_per_mixture=lanes, block=block)
-    api.flash(*args, out=out, lanes_per_mixture=lanes, block=block)
+    kw = dict(lanes_per_mixture=la, lanes_split=lb, block=block)
+    out = api.flash(*args, **kw)
+    api.flash(*args, out=out, **kw)
     ts = []
     for _ in range(reps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        api.flash(*args, out=out, lanes_per_mixture=lanes, block=block)
+        api.flash(*args, out=out, **kw)
         torch.cuda.synchronize()
         ts.append(time.perf_counter() - t0)
     return float(np.median(ts))
 
 
-def header(lanes, blocks) -> str:
+def header(lanes_sa, lanes_sp, blocks) -> str:
     def row(v):
         return ", ".join(str(x) for x in v)
     return f"""// tuned_gfx950.hpp -- launch shape of the persistent flash per component
-// count on gfx950: lanes per mixture of the trust-region stages (1: one
-// mixture per lane; 16 or 32: one group of that many lanes per mixture) and
-// threads per block.  Written by autotune.py from timed runs (the timings
-// are in the autotune summary next to the profiles).
+// count on gfx950: lanes per mixture of the stability and of the split
+// trust-region stage (1: one mixture per lane; 16 or 32: one group of that
+// many lanes per mixture) and threads per block.  Written by autotune.py
+// from timed runs (the timings are in the autotune summary next to the
+// profiles).
 #pragma once
 
 namespace ptf {{
 
-constexpr int kTunedLanes[21] = {{{row(lanes)}}};
+constexpr int kTunedLanesSa[21] = {{{row(lanes_sa)}}};
+constexpr int kTunedLanesSp[21] = {{{row(lanes_sp)}}};
 constexpr int kTunedBlock[21] = {{{row(blocks)}}};
 
-constexpr int tuned_lanes(int nc)
+constexpr int tuned_lanes_sa(int nc)
 {{
-    return (nc >= 0 && nc <= 20) ? kTunedLanes[nc] : 1;
+    return (nc >= 0 && nc <= 20) ? kTunedLanesSa[nc] : 1;
+}}
+
+constexpr int tuned_lanes_sp(int nc)
+{{
+    return (nc >= 0 && nc <= 20) ? kTunedLanesSp[nc] : 1;
 }}
 
 constexpr int tuned_block(int nc)
@@ -87,7 +101,8 @@ def main():
     import torch
     lo, hi = (int(x) for x in a.nc.split("-"))
     dev = torch.device("cuda", 0)
-    lanes = [1] * 21
+    lanes_sa = [1] * 21
+    lanes_sp = [1] * 21
     blocks = [256] * 21
     lines = ["# Launch-shape autotune (gfx950)", "",
              f"Command: `python -m paper_2205_03090_amd.autotune --out <dir> --n {a.n} "
@@ -95,27 +110,28 @@ def main():
              f"Sample per nc: {a.n} mixtures of uniform_workload(seed 30000 + nc, alpha 0.5, "
              "T in [200, 600] K, P in [1e5, 2e7] Pa, one shared set); median of "
              f"{a.reps} timed flashes after two untimed ones.", "",
-             "| nc | lanes | block | ms | flashes/s |", "|---|---|---|---|---|"]
+             "| nc | lanes (stability TR) | lanes (split TR) | block | ms | flashes/s |",
+             "|---|---|---|---|---|---|"]
     for nc in range(lo, hi + 1):
         w = workloads.uniform_workload(f"tune{nc}", 30_000 + nc, a.n, nc, 0.5,
                                        (200.0, 600.0), (1.0e5, 2.0e7))
         t = lambda x: torch.as_tensor(x, dtype=torch.float64, device=dev).contiguous()
         args = [t(v) for v in (w.z, w.T, w.P, w.Tc, w.Pc, w.omega, w.kij)]
         best = None
-        for (l, b) in candidates(nc):
-            dt = time_one(args, l, b, a.reps)
-            lines.append(f"| {nc} | {l} | {b} | {dt * 1e3:.3f} | {a.n / dt / 1e6:.1f} M |")
-            print(f"nc {nc} lanes {l} block {b}: {dt * 1e3:.3f} ms", flush=True)
+        for (la, lb, k) in candidates(nc):
+            dt = time_one(args, la, lb, k, a.reps)
+            lines.append(f"| {nc} | {la} | {lb} | {k} | {dt * 1e3:.3f} | {a.n / dt / 1e6:.1f} M |")
+            print(f"nc {nc} lanes {la}/{lb} block {k}: {dt * 1e3:.3f} ms", flush=True)
             if best is None or dt < best[0]:
-                best = (dt, l, b)
-        lanes[nc], blocks[nc] = best[1], best[2]
-        lines.append(f"| **{nc}** | **{best[1]}** | **{best[2]}** | chosen | |")
+                best = (dt, la, lb, k)
+        lanes_sa[nc], lanes_sp[nc], blocks[nc] = best[1], best[2], best[3]
+        lines.append(f"| **{nc}** | **{best[1]}** | **{best[2]}** | **{best[3]}** | chosen | |")
     os.makedirs(a.out, exist_ok=True)
     with open(os.path.join(a.out, "tuned_gfx950.hpp"), "w") as f:
-        f.write(header(lanes, blocks))
+        f.write(header(lanes_sa, lanes_sp, blocks))
     with open(os.path.join(a.out, "autotune_gfx950.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
-    print("lanes", lanes, "\nblocks", blocks)
+    print("lanes", lanes_sa, lanes_sp, "\nblocks", blocks)
 
 
 if __name__ == "__main__":

@@ -605,17 +605,32 @@ int run_persistent_stage_group(const Ctx<NC> &c, const ptflash_problem *p,
     return hipGetLastError() == hipSuccess ? PTFLASH_OK : PTFLASH_EHIP;
 }
 
-// Lanes per mixture of the trust-region stages: the option, or the tuned
-// choice for this nc; 0 when the value is not available for this nc.
+// Lanes per mixture of a trust-region stage, or 0 when l is not available
+// for this nc.
 template <int NC>
-int lanes_for(const ptflash_options *o)
+int lanes_ok(int l)
 {
-    const int l = o->lanes_per_mixture > 0 ? o->lanes_per_mixture : tuned_lanes(NC);
     if (l == 1) return 1;
     if (NC < kGroupMinNc) return 0;
     if (l == 16 && NC <= 16) return 16;
     if (l == 32 && NC <= 32) return 32;
     return 0;
+}
+
+// The stability trust region: the option, or the tuned choice for this nc.
+template <int NC>
+int lanes_sa(const ptflash_options *o)
+{
+    return lanes_ok<NC>(o->lanes_per_mixture > 0 ? o->lanes_per_mixture : tuned_lanes_sa(NC));
+}
+
+// The split trust region: lanes_split, else lanes_per_mixture, else tuned.
+template <int NC>
+int lanes_sp(const ptflash_options *o)
+{
+    const int l = o->lanes_split > 0 ? o->lanes_split
+                  : o->lanes_per_mixture > 0 ? o->lanes_per_mixture : tuned_lanes_sp(NC);
+    return lanes_ok<NC>(l);
 }
 
 // One trust-region stage (Item1: one mixture per lane; ItemG<G>: groups).
@@ -640,8 +655,8 @@ template <int NC, bool PM>
 int launch_persistent(const FlashArgs &a, const ptflash_problem *p, const ptflash_options *o,
                       void *ws, hipStream_t s)
 {
-    const int lanes = lanes_for<NC>(o);
-    if (lanes == 0) return PTFLASH_EINVAL;
+    const int lsa = lanes_sa<NC>(o), lsp = lanes_sp<NC>(o);
+    if (lsa == 0 || lsp == 0) return PTFLASH_EINVAL;
     Ctx<NC> c;
     char *tail;
     setup_ctx<NC>(c, a, p->n, ws, &tail);
@@ -650,10 +665,10 @@ int launch_persistent(const FlashArgs &a, const ptflash_problem *p, const ptflas
     if ((rc = run_persistent_stage<FeedItem<NC, PM>, NC>(c, p, o, kTake0 + 0, s))) return rc;
     if ((rc = run_persistent_stage<PreSsItem<NC, PM>, NC>(c, p, o, kTake0 + 1, s))) return rc;
     if ((rc = run_persistent_stage<SaSsItem<NC, PM>, NC>(c, p, o, kTake0 + 2, s))) return rc;
-    if ((rc = run_tr_stage<SaTrItem, SaTrGroup, NC, PM>(c, p, o, lanes, kTake0 + 3, s))) return rc;
+    if ((rc = run_tr_stage<SaTrItem, SaTrGroup, NC, PM>(c, p, o, lsa, kTake0 + 3, s))) return rc;
     if ((rc = run_persistent_stage<SaFinItem<NC, PM>, NC>(c, p, o, kTake0 + 4, s))) return rc;
     if ((rc = run_persistent_stage<SpSsItem<NC, PM>, NC>(c, p, o, kTake0 + 5, s))) return rc;
-    if ((rc = run_tr_stage<SpNtItem, SpNtGroup, NC, PM>(c, p, o, lanes, kTake0 + 6, s))) return rc;
+    if ((rc = run_tr_stage<SpNtItem, SpNtGroup, NC, PM>(c, p, o, lsp, kTake0 + 6, s))) return rc;
     return PTFLASH_OK;
 }
 

@@ -307,7 +307,9 @@ static bool options_ok(const ptflash_options *o)
            o->tol_polish > 0 && o->eps_tm >= 0 &&
            (o->form == PTFLASH_FORM_PERSISTENT || o->form == PTFLASH_FORM_PLAIN) &&
            (o->lanes_per_mixture == 0 || o->lanes_per_mixture == 1 ||
-            o->lanes_per_mixture == 16 || o->lanes_per_mixture == 32);
+            o->lanes_per_mixture == 16 || o->lanes_per_mixture == 32) &&
+           (o->lanes_split == 0 || o->lanes_split == 1 || o->lanes_split == 16 ||
+            o->lanes_split == 32);
 }
 
 }  // namespace ptf
@@ -337,6 +339,7 @@ void ptflash_default_options(ptflash_options *o)
     o->block = 0;
     o->grid = 0;
     o->lanes_per_mixture = 0;
+    o->lanes_split = 0;
 }
 
 int32_t ptflash_max_nc(void) { return kMaxNc; }

@@ -33,9 +33,9 @@ def _assert_parity(rep, path_agree=0.97):
     assert rep["ss_path_agree"] >= path_agree
 
 
-def _check(w, lanes, tag):
-    print(f"case {tag} nc={w.nc} lanes={lanes} n={w.n}", flush=True)
-    g = _run(w, lanes_per_mixture=lanes)
+def _check(w, lanes, tag, split=0):
+    print(f"case {tag} nc={w.nc} lanes={lanes}/{split} n={w.n}", flush=True)
+    g = _run(w, lanes_per_mixture=lanes, lanes_split=split)
     inv = invariants(w, g)
     print(f"[{tag} invariants] {inv}", flush=True)
     assert inv["mass_balance"] < 1e-13 and inv["sum_x"] < 1e-13 and inv["sum_y"] < 1e-13
@@ -72,6 +72,14 @@ def test_group_per_mixture_sets_parity(nc, lanes):
     w = workloads.uniform_workload(f"pm{nc}", 2000 + nc, 3000, nc, 0.5, (200.0, 600.0),
                                    (1e5, 2e7), per_mixture=True)
     _check(w, lanes, f"group per-mixture nc{nc}")
+
+
+@pytest.mark.parametrize("nc,sa,sp", [(20, 32, 1), (20, 1, 32), (14, 16, 1)])
+def test_mixed_stage_widths_parity(nc, sa, sp):
+    # the two trust-region stages with different lanes per mixture
+    w = workloads.uniform_workload(f"mx{nc}", 3000 + nc, 3000, nc, 0.5, (200.0, 600.0),
+                                   (1e5, 2e7))
+    _check(w, sa, f"mixed nc{nc}", split=sp)
 
 
 def test_group_deterministic_across_runs_and_grids():
@@ -122,6 +130,12 @@ def test_lanes_option_checked():
         _run(w20, lanes_per_mixture=16)   # a group smaller than nc
     with pytest.raises(RuntimeError):
         _run(w20, lanes_per_mixture=8)    # not a supported width
+    with pytest.raises(RuntimeError):
+        _run(w20, lanes_per_mixture=1, lanes_split=16)   # split group too small
+    with pytest.raises(RuntimeError):
+        _run(w, lanes_split=32)   # nc = 4
+    assert o.lanes_split == 0
     _run(w20, lanes_per_mixture=32)
     _run(w20, lanes_per_mixture=1)
+    _run(w20, lanes_per_mixture=1, lanes_split=32)
     assert L is not None and isinstance(o, C.Structure)
