@@ -81,7 +81,8 @@ def uniform_workload(name: str, seed: int, n: int, nc: int, alpha: float,
 
 # Named workloads.  Sizes and distributions are those of the flash
 # configurations this library is measured on.
-SEEDS = {"nc3": 20_250_001, "nc8": 20_250_002, "nc10": 20_250_004, "nc20": 20_250_005}
+SEEDS = {"nc3": 20_250_001, "nc8": 20_250_002, "ragged": 20_250_003, "nc10": 20_250_004,
+         "nc20": 20_250_005}
 
 
 def nc3_workload(n: int = 10_000, seed: int = SEEDS["nc3"]) -> Workload:
@@ -135,13 +136,61 @@ class RaggedWorkload:
 
     def group(self, nc: int):
         """(indices, per-mixture-set Workload) of the mixtures with this nc."""
-        idx = np.where(self.nc_of == nc)[0]
+        return self.select(np.where(self.nc_of == nc)[0], nc)
+
+    def select(self, idx, nc: int):
+        """(idx, per-mixture-set Workload) of the given mixtures, all of which
+        have this nc."""
+        idx = np.asarray(idx)
         rows = (self.off[idx][:, None] + np.arange(nc)[None, :])
         kb = (self.koff[idx][:, None] + np.arange(nc * nc)[None, :])
         w = Workload(f"{self.name}_nc{nc}", len(idx), nc, self.z[rows], self.T[idx],
                      self.P[idx], self.Tc[rows], self.Pc[rows], self.omega[rows],
                      self.kij[kb].reshape(len(idx), nc, nc), True)
         return idx, w
+
+
+def ragged_workload_vec(name: str, seed: int, n: int, nc_set=(2, 4, 6, 8, 12, 16, 20),
+                        alpha: float = 0.5, T_range=(200.0, 600.0),
+                        P_range=(1.0e5, 2.0e7)) -> RaggedWorkload:
+    """The distributions of ragged_workload, drawn group by group for large n:
+    nc ~ U(nc_set) per mixture; then, for each nc of nc_set in increasing
+    order, the component sets of all mixtures with that nc (all their Tc, then
+    Pc, then omega, then the strict upper k triangles in row-major order) and
+    their feeds z ~ Dirichlet(alpha * 1); then T and P for all mixtures."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nc_of = rng.choice(np.asarray(nc_set, dtype=np.int32), size=n).astype(np.int32)
+    off = np.zeros(n + 1, dtype=np.int64)
+    off[1:] = np.cumsum(nc_of)
+    ksz = nc_of.astype(np.int64) ** 2
+    koff = np.zeros(n, dtype=np.int64)
+    koff[1:] = np.cumsum(ksz)[:-1]
+    tot, ktot = int(off[-1]), int(ksz.sum())
+    z = np.empty(tot); Tc = np.empty(tot); Pc = np.empty(tot); om = np.empty(tot)
+    kij = np.empty(ktot)
+    for nc in sorted(set(int(v) for v in nc_set)):
+        idx = np.where(nc_of == nc)[0]
+        cnt = len(idx)
+        rows = (off[idx][:, None] + np.arange(nc)[None, :]).ravel()
+        Tc[rows] = rng.uniform(190.0, 620.0, (cnt, nc)).ravel()
+        Pc[rows] = rng.uniform(2.0e6, 5.0e6, (cnt, nc)).ravel()
+        om[rows] = rng.uniform(0.01, 0.5, (cnt, nc)).ravel()
+        iu = np.triu_indices(nc, 1)
+        k = np.zeros((cnt, nc, nc))
+        k[:, iu[0], iu[1]] = rng.uniform(0.0, 0.15, (cnt, len(iu[0])))
+        k += k.transpose(0, 2, 1)
+        kij[(koff[idx][:, None] + np.arange(nc * nc)[None, :]).ravel()] = k.reshape(-1)
+        del k
+        z[rows] = rng.dirichlet(np.full(nc, alpha), size=cnt).ravel()
+    T = rng.uniform(T_range[0], T_range[1], n)
+    P = rng.uniform(P_range[0], P_range[1], n)
+    return RaggedWorkload(name, n, nc_of, off, koff, z, T, P, Tc, Pc, om, kij)
+
+
+def ragged_4m_workload(n: int = 4_000_000, seed: int = SEEDS["ragged"]) -> RaggedWorkload:
+    """4,000,000 mixtures, nc ~ U{2,4,6,8,12,16,20}, one component set per
+    mixture, z ~ Dir(0.5 * 1), T ~ U[200,600] K, P ~ U[1e5, 2e7] Pa."""
+    return ragged_workload_vec("ragged_4m", seed, n)
 
 
 def ragged_workload(name: str, seed: int, n: int, nc_set=(2, 4, 6, 8, 12, 16, 20),
