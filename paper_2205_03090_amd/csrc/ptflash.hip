@@ -180,16 +180,26 @@ struct BucketStarts {
 };
 
 // Counting sort of the mixture ids by bucket (the order inside a bucket is
-// arbitrary; every mixture's result depends on its own data only).
+// arbitrary; every mixture's result depends on its own data only).  Ranks
+// inside a block come from LDS atomics; each block then claims its range of
+// every bucket with one device atomic (per-mixture device atomics on the
+// few bucket counters serialise).
 __global__ void __launch_bounds__(kBlock)
 ragged_sort(int64_t n, const int32_t *__restrict__ nc_of, const int64_t *__restrict__ off,
             BucketStarts st, unsigned long long *cursor, uint32_t *ids)
 {
+    __shared__ unsigned int cnt[kBuckets];
+    __shared__ unsigned long long base[kBuckets];
+    if (threadIdx.x < kBuckets) cnt[threadIdx.x] = 0u;
+    __syncthreads();
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= n) return;
-    const int b = ragged_bucket(m, nc_of, off);
-    const unsigned long long k = atomicAdd(&cursor[b], 1ull);
-    ids[st.s[b] + (int64_t)k] = (uint32_t)m;
+    const int b = m < n ? ragged_bucket(m, nc_of, off) : 0;
+    const unsigned int r = m < n ? atomicAdd(&cnt[b], 1u) : 0u;
+    __syncthreads();
+    if (threadIdx.x < kBuckets && cnt[threadIdx.x] > 0u)
+        base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], (unsigned long long)cnt[threadIdx.x]);
+    __syncthreads();
+    if (m < n) ids[st.s[b] + (int64_t)(base[b] + r)] = (uint32_t)m;
 }
 
 struct RaggedIn {
@@ -206,43 +216,92 @@ struct Uniform {   // one gathered uniform-nc chunk
     uint32_t *flops;
 };
 
+// Gather of one uniform chunk, one thread per value (coalesced stores, and
+// loads that walk each mixture's contiguous rows): the per-component rows
+// (z, Tc, Pc, omega; T and P with component 0) ...
+template <int NC>
 __global__ void __launch_bounds__(kBlock)
-ragged_gather(int64_t cnt, int nc, const uint32_t *__restrict__ ids, RaggedIn in, Uniform u)
+ragged_gather_rows(int64_t cnt, const uint32_t *__restrict__ ids, RaggedIn in, Uniform u)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= cnt) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cnt * NC) return;
+    const int64_t j = t / NC;
+    const int e = (int)(t - j * NC);
     const int64_t m = ids[j];
-    const int64_t o = in.off[m], ko = in.koff[m];
-    u.T[j] = in.T[m];
-    u.P[j] = in.P[m];
-    for (int i = 0; i < nc; ++i) {
-        u.z[j * nc + i] = in.z[o + i];
-        u.Tc[j * nc + i] = in.Tc[o + i];
-        u.Pc[j * nc + i] = in.Pc[o + i];
-        u.om[j * nc + i] = in.om[o + i];
+    const int64_t o = in.off[m] + e;
+    u.z[t] = in.z[o];
+    u.Tc[t] = in.Tc[o];
+    u.Pc[t] = in.Pc[o];
+    u.om[t] = in.om[o];
+    if (e == 0) {
+        u.T[j] = in.T[m];
+        u.P[j] = in.P[m];
     }
-    for (int i = 0; i < nc * nc; ++i) u.K[j * nc * nc + i] = in.K[ko + i];
 }
 
+// ... and the k blocks.
+template <int NC>
 __global__ void __launch_bounds__(kBlock)
-ragged_scatter(int64_t cnt, int nc, const uint32_t *__restrict__ ids, const int64_t *off,
-               Uniform u, ptflash_result r)
+ragged_gather_k(int64_t cnt, const uint32_t *__restrict__ ids, RaggedIn in, Uniform u)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= cnt) return;
-    const int64_t m = ids[j];
-    const int64_t o = off[m];
-    r.label[m] = u.label[j];
-    r.beta[m] = u.beta[j];
-    for (int i = 0; i < nc; ++i) {
-        r.x[o + i] = u.x[j * nc + i];
-        r.y[o + i] = u.y[j * nc + i];
-    }
-    if (r.iters)
-        for (int k = 0; k < PTFLASH_NITERS; ++k) r.iters[m * PTFLASH_NITERS + k] = u.iters[j * PTFLASH_NITERS + k];
-    if (r.status) r.status[m] = u.status[j];
-    if (r.flops) r.flops[m] = u.flops[j];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cnt * NC * NC) return;
+    const int64_t j = t / (NC * NC);
+    const int e = (int)(t - j * (NC * NC));
+    u.K[t] = in.K[in.koff[ids[j]] + e];
 }
+
+// Scatter of one chunk's outputs, one thread per x/y value (per-mixture
+// fields with component 0).
+template <int NC>
+__global__ void __launch_bounds__(kBlock)
+ragged_scatter_rows(int64_t cnt, const uint32_t *__restrict__ ids, const int64_t *off, Uniform u,
+                    ptflash_result r)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cnt * NC) return;
+    const int64_t j = t / NC;
+    const int e = (int)(t - j * NC);
+    const int64_t m = ids[j];
+    const int64_t o = off[m] + e;
+    r.x[o] = u.x[t];
+    r.y[o] = u.y[t];
+    if (e == 0) {
+        r.label[m] = u.label[j];
+        r.beta[m] = u.beta[j];
+        if (r.iters)
+            for (int k = 0; k < PTFLASH_NITERS; ++k)
+                r.iters[m * PTFLASH_NITERS + k] = u.iters[j * PTFLASH_NITERS + k];
+        if (r.status) r.status[m] = u.status[j];
+        if (r.flops) r.flops[m] = u.flops[j];
+    }
+}
+
+template <int NC>
+void ragged_move(bool gather, int64_t cnt, const uint32_t *ids, const RaggedIn &in,
+                 const Uniform &u, const int64_t *off, const ptflash_result &r, hipStream_t s)
+{
+    auto grid = [](int64_t k) { return dim3((unsigned)((k + kBlock - 1) / kBlock)); };
+    if (gather) {
+        hipLaunchKernelGGL(ragged_gather_rows<NC>, grid(cnt * NC), dim3(kBlock), 0, s, cnt, ids,
+                           in, u);
+        hipLaunchKernelGGL(ragged_gather_k<NC>, grid(cnt * NC * NC), dim3(kBlock), 0, s, cnt,
+                           ids, in, u);
+    } else {
+        hipLaunchKernelGGL(ragged_scatter_rows<NC>, grid(cnt * NC), dim3(kBlock), 0, s, cnt,
+                           ids, off, u, r);
+    }
+}
+
+template <int NC>
+struct RaggedMove {
+    static void run(int nc, bool gather, int64_t cnt, const uint32_t *ids, const RaggedIn &in,
+                    const Uniform &u, const int64_t *off, const ptflash_result &r, hipStream_t s)
+    {
+        if (nc == NC) ragged_move<NC>(gather, cnt, ids, in, u, off, r, s);
+        else if constexpr (NC < kMaxNc) RaggedMove<NC + 1>::run(nc, gather, cnt, ids, in, u, off, r, s);
+    }
+};
 
 // Mixtures whose nc or row count is unusable: single phase, INVALID, with
 // the raw z rows they do have copied to x and y.
@@ -518,8 +577,7 @@ int ptflash_flash_ragged(const ptflash_ragged_problem *p, const ptflash_options 
         for (int64_t c0 = 0; c0 < (int64_t)hc[nc]; c0 += ch) {
             const int64_t cnt = ((int64_t)hc[nc] - c0) < ch ? ((int64_t)hc[nc] - c0) : ch;
             const uint32_t *cid = ids + st.s[nc] + c0;
-            const unsigned g = (unsigned)((cnt + kBlock - 1) / kBlock);
-            hipLaunchKernelGGL(ragged_gather, dim3(g), dim3(kBlock), 0, s, cnt, nc, cid, in, u);
+            RaggedMove<kMinNc>::run(nc, true, cnt, cid, in, u, p->off, rr, s);
             ptflash_problem sub{cnt, nc, 1, u.z, u.T, u.P, u.Tc, u.Pc, u.om, u.K};
             ptflash_result sr{u.label, u.beta, u.x, u.y, u.iters, u.status, u.flops, nullptr};
             if (fws_bytes < ptflash_workspace_bytes(&sub, o)) return PTFLASH_EWORKSPACE;
@@ -527,8 +585,7 @@ int ptflash_flash_ragged(const ptflash_ragged_problem *p, const ptflash_options 
             fill_args(a, &sub, o, &sr);
             int rc = Dispatch<FlashF>::run(nc, a, &sub, o, fws, s);
             if (rc) return rc;
-            hipLaunchKernelGGL(ragged_scatter, dim3(g), dim3(kBlock), 0, s, cnt, nc, cid, p->off,
-                               u, rr);
+            RaggedMove<kMinNc>::run(nc, false, cnt, cid, in, u, p->off, rr, s);
             if (hipGetLastError() != hipSuccess) return PTFLASH_EHIP;
         }
     }
