@@ -1,14 +1,16 @@
-"""Chooses, per component count, the launch shape of the persistent flash on
-this GPU: the lanes per mixture of each of the two trust-region stages (1, or
-a group of 16 or 32 lanes) and the threads per block, by timing every
-candidate on a seeded sample workload.
+"""Chooses, per component count and layout of the component sets, the launch
+shape of the persistent flash on this GPU: the lanes per mixture of each of
+the two trust-region stages (1, or a group of 16 or 32 lanes) and the threads
+per block, by timing every candidate on seeded sample workloads.
 
-  python -m paper_2205_03090_amd.autotune --out DIR [--n 200000] [--reps 3]
+  python -m paper_2205_03090_amd.autotune --out DIR [--n 4000000] [--n-pm 1000000]
 
 writes DIR/tuned_gfx950.hpp (the table the library compiles in as its
 default, csrc/tuned_gfx950.hpp) and DIR/autotune_gfx950.md (the timings).
 The sample for nc is uniform_workload(seed 30000 + nc, alpha 0.5,
-T in [200, 600] K, P in [1e5, 2e7] Pa, one shared component set).
+T in [200, 600] K, P in [1e5, 2e7] Pa) with one shared component set, and
+per_mixture_workload_vec(seed 31000 + nc, same distributions) with one set
+per mixture.
 """
 from __future__ import annotations
 
@@ -56,35 +58,40 @@ def time_one(args, la: int, lb: int, block: int, reps: int) -> float:
 
 
 def header(lanes_sa, lanes_sp, blocks) -> str:
+    """lanes_sa etc.: [layout][nc], layout 0 = shared set, 1 = one per mixture."""
     def row(v):
-        return ", ".join(str(x) for x in v)
+        return "{" + ", ".join(str(x) for x in v) + "}"
     return f"""// tuned_gfx950.hpp -- launch shape of the persistent flash per component
 // count on gfx950: lanes per mixture of the stability and of the split
 // trust-region stage (1: one mixture per lane; 16 or 32: one group of that
-// many lanes per mixture) and threads per block.  Written by autotune.py
-// from timed runs (the timings are in the autotune summary next to the
+// many lanes per mixture) and threads per block, for a shared component set
+// (row 0) and for one set per mixture (row 1).  Written by autotune.py from
+// timed runs (the timings are in the autotune summary next to the
 // profiles).
 #pragma once
 
 namespace ptf {{
 
-constexpr int kTunedLanesSa[21] = {{{row(lanes_sa)}}};
-constexpr int kTunedLanesSp[21] = {{{row(lanes_sp)}}};
-constexpr int kTunedBlock[21] = {{{row(blocks)}}};
+constexpr int kTunedLanesSa[2][21] = {{{row(lanes_sa[0])},
+                                       {row(lanes_sa[1])}}};
+constexpr int kTunedLanesSp[2][21] = {{{row(lanes_sp[0])},
+                                       {row(lanes_sp[1])}}};
+constexpr int kTunedBlock[2][21] = {{{row(blocks[0])},
+                                     {row(blocks[1])}}};
 
-constexpr int tuned_lanes_sa(int nc)
+constexpr int tuned_lanes_sa(int nc, bool pm)
 {{
-    return (nc >= 0 && nc <= 20) ? kTunedLanesSa[nc] : 1;
+    return (nc >= 0 && nc <= 20) ? kTunedLanesSa[pm ? 1 : 0][nc] : 1;
 }}
 
-constexpr int tuned_lanes_sp(int nc)
+constexpr int tuned_lanes_sp(int nc, bool pm)
 {{
-    return (nc >= 0 && nc <= 20) ? kTunedLanesSp[nc] : 1;
+    return (nc >= 0 && nc <= 20) ? kTunedLanesSp[pm ? 1 : 0][nc] : 1;
 }}
 
-constexpr int tuned_block(int nc)
+constexpr int tuned_block(int nc, bool pm)
 {{
-    return (nc >= 0 && nc <= 20) ? kTunedBlock[nc] : 256;
+    return (nc >= 0 && nc <= 20) ? kTunedBlock[pm ? 1 : 0][nc] : 256;
 }}
 
 }}  // namespace ptf
@@ -94,38 +101,53 @@ constexpr int tuned_block(int nc)
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
-    ap.add_argument("--n", type=int, default=200_000)
+    ap.add_argument("--n", type=int, default=4_000_000)
+    ap.add_argument("--n-pm", type=int, default=1_000_000)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--nc", type=str, default=f"2-{_build.MAX_NC}")
     a = ap.parse_args()
     import torch
     lo, hi = (int(x) for x in a.nc.split("-"))
     dev = torch.device("cuda", 0)
-    lanes_sa = [1] * 21
-    lanes_sp = [1] * 21
-    blocks = [256] * 21
+    lanes_sa = [[1] * 21, [1] * 21]
+    lanes_sp = [[1] * 21, [1] * 21]
+    blocks = [[256] * 21, [256] * 21]
     lines = ["# Launch-shape autotune (gfx950)", "",
              f"Command: `python -m paper_2205_03090_amd.autotune --out <dir> --n {a.n} "
-             f"--reps {a.reps} --nc {a.nc}`", "",
-             f"Sample per nc: {a.n} mixtures of uniform_workload(seed 30000 + nc, alpha 0.5, "
-             "T in [200, 600] K, P in [1e5, 2e7] Pa, one shared set); median of "
-             f"{a.reps} timed flashes after two untimed ones.", "",
-             "| nc | lanes (stability TR) | lanes (split TR) | block | ms | flashes/s |",
-             "|---|---|---|---|---|---|"]
-    for nc in range(lo, hi + 1):
-        w = workloads.uniform_workload(f"tune{nc}", 30_000 + nc, a.n, nc, 0.5,
-                                       (200.0, 600.0), (1.0e5, 2.0e7))
-        t = lambda x: torch.as_tensor(x, dtype=torch.float64, device=dev).contiguous()
-        args = [t(v) for v in (w.z, w.T, w.P, w.Tc, w.Pc, w.omega, w.kij)]
-        best = None
-        for (la, lb, k) in candidates(nc):
-            dt = time_one(args, la, lb, k, a.reps)
-            lines.append(f"| {nc} | {la} | {lb} | {k} | {dt * 1e3:.3f} | {a.n / dt / 1e6:.1f} M |")
-            print(f"nc {nc} lanes {la}/{lb} block {k}: {dt * 1e3:.3f} ms", flush=True)
-            if best is None or dt < best[0]:
-                best = (dt, la, lb, k)
-        lanes_sa[nc], lanes_sp[nc], blocks[nc] = best[1], best[2], best[3]
-        lines.append(f"| **{nc}** | **{best[1]}** | **{best[2]}** | **{best[3]}** | chosen | |")
+             f"--n-pm {a.n_pm} --reps {a.reps} --nc {a.nc}`", "",
+             f"Samples per nc: {a.n} mixtures of uniform_workload(seed 30000 + nc, alpha 0.5, "
+             "T in [200, 600] K, P in [1e5, 2e7] Pa, one shared set), and "
+             f"{a.n_pm} mixtures of per_mixture_workload_vec(seed 31000 + nc, the same "
+             f"distributions, one set per mixture); median of {a.reps} timed flashes "
+             "after two untimed ones.", "",
+             "| sets | nc | lanes (stability TR) | lanes (split TR) | block | ms | flashes/s |",
+             "|---|---|---|---|---|---|---|"]
+    t = lambda x: torch.as_tensor(x, dtype=torch.float64, device=dev).contiguous()
+    for pm in (0, 1):
+        for nc in range(lo, hi + 1):
+            if pm:
+                n = a.n_pm
+                w = workloads.per_mixture_workload_vec(f"tunepm{nc}", 31_000 + nc, n, nc, 0.5)
+            else:
+                n = a.n
+                w = workloads.uniform_workload(f"tune{nc}", 30_000 + nc, n, nc, 0.5,
+                                               (200.0, 600.0), (1.0e5, 2.0e7))
+            args = [t(v) for v in (w.z, w.T, w.P, w.Tc, w.Pc, w.omega, w.kij)]
+            del w
+            best = None
+            tag = "per mixture" if pm else "shared"
+            for (la, lb, k) in candidates(nc):
+                dt = time_one(args, la, lb, k, a.reps)
+                lines.append(f"| {tag} | {nc} | {la} | {lb} | {k} | {dt * 1e3:.3f} | "
+                             f"{n / dt / 1e6:.1f} M |")
+                print(f"{tag} nc {nc} lanes {la}/{lb} block {k}: {dt * 1e3:.3f} ms", flush=True)
+                if best is None or dt < best[0]:
+                    best = (dt, la, lb, k)
+            lanes_sa[pm][nc], lanes_sp[pm][nc], blocks[pm][nc] = best[1], best[2], best[3]
+            lines.append(f"| {tag} | **{nc}** | **{best[1]}** | **{best[2]}** | **{best[3]}** "
+                         "| chosen | |")
+            del args
+            torch.cuda.empty_cache()
     os.makedirs(a.out, exist_ok=True)
     with open(os.path.join(a.out, "tuned_gfx950.hpp"), "w") as f:
         f.write(header(lanes_sa, lanes_sp, blocks))

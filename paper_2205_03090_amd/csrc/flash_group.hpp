@@ -362,6 +362,7 @@ __device__ __forceinline__ void load_kappa(double (&kap)[NC], const Ctx<NC> &c, 
 template <int NC, bool PM, int G>
 struct SaTrGroup {
     static constexpr int WAVES = 2;   // minimum wavefronts per SIMD
+    static constexpr bool kPerMixture = PM;   // one component set per mixture
     static constexpr uint32_t OUT = 0u;
     static constexpr int LIST = L_SATR;
     static constexpr int LIST2 = -1;
@@ -486,6 +487,7 @@ struct SaTrGroup {
 template <int NC, bool PM, int G>
 struct SpNtGroup {
     static constexpr int WAVES = 2;   // minimum wavefronts per SIMD
+    static constexpr bool kPerMixture = PM;   // one component set per mixture
     static constexpr uint32_t OUT = 0u;
     static constexpr int LIST = L_NT;
     static constexpr int LIST2 = L_NTP;

@@ -583,7 +583,7 @@ template <class Item, int NC>
 int run_persistent_stage(const Ctx<NC> &c, const ptflash_problem *p,
                                 const ptflash_options *o, int take_slot, hipStream_t s)
 {
-    const int block = o->block > 0 ? o->block : tuned_block(NC);
+    const int block = o->block > 0 ? o->block : tuned_block(NC, Item::kPerMixture);
     if (block % 64 != 0 || block > kBlock) return PTFLASH_EINVAL;
     const int grid = grid_for((const void *)stage_persistent<Item, NC>, block, o->grid);
     if (grid <= 0) return PTFLASH_EHIP;
@@ -596,7 +596,7 @@ template <class Item, int NC, int G>
 int run_persistent_stage_group(const Ctx<NC> &c, const ptflash_problem *p,
                                const ptflash_options *o, int take_slot, hipStream_t s)
 {
-    const int block = o->block > 0 ? o->block : tuned_block(NC);
+    const int block = o->block > 0 ? o->block : tuned_block(NC, Item::kPerMixture);
     if (block % 64 != 0 || block > kBlock) return PTFLASH_EINVAL;
     const int grid = grid_for((const void *)stage_persistent_group<Item, NC, G>, block, o->grid);
     if (grid <= 0) return PTFLASH_EHIP;
@@ -617,19 +617,21 @@ int lanes_ok(int l)
     return 0;
 }
 
-// The stability trust region: the option, or the tuned choice for this nc.
+// The stability trust region: the option, or the tuned choice for this nc
+// and layout of the component sets (pm: one set per mixture).
 template <int NC>
-int lanes_sa(const ptflash_options *o)
+int lanes_sa(const ptflash_options *o, bool pm)
 {
-    return lanes_ok<NC>(o->lanes_per_mixture > 0 ? o->lanes_per_mixture : tuned_lanes_sa(NC));
+    return lanes_ok<NC>(o->lanes_per_mixture > 0 ? o->lanes_per_mixture
+                                                 : tuned_lanes_sa(NC, pm));
 }
 
 // The split trust region: lanes_split, else lanes_per_mixture, else tuned.
 template <int NC>
-int lanes_sp(const ptflash_options *o)
+int lanes_sp(const ptflash_options *o, bool pm)
 {
     const int l = o->lanes_split > 0 ? o->lanes_split
-                  : o->lanes_per_mixture > 0 ? o->lanes_per_mixture : tuned_lanes_sp(NC);
+                  : o->lanes_per_mixture > 0 ? o->lanes_per_mixture : tuned_lanes_sp(NC, pm);
     return lanes_ok<NC>(l);
 }
 
@@ -655,7 +657,7 @@ template <int NC, bool PM>
 int launch_persistent(const FlashArgs &a, const ptflash_problem *p, const ptflash_options *o,
                       void *ws, hipStream_t s)
 {
-    const int lsa = lanes_sa<NC>(o), lsp = lanes_sp<NC>(o);
+    const int lsa = lanes_sa<NC>(o, PM), lsp = lanes_sp<NC>(o, PM);
     if (lsa == 0 || lsp == 0) return PTFLASH_EINVAL;
     Ctx<NC> c;
     char *tail;

@@ -293,6 +293,7 @@ __device__ __forceinline__ void route_mixture(MixRec<NC> &r, Outbox &ob, int64_t
 template <int NC, bool PM>
 struct FeedItem {
     static constexpr int WAVES = 1;   // minimum wavefronts per SIMD
+    static constexpr bool kPerMixture = PM;   // one component set per mixture
     static constexpr uint32_t OUT = (1u << L_SA) | (1u << L_SAFIN) | (1u << L_PRE);   // lists the steps append to
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = -1;   // input: mixtures 0..n-1
@@ -378,6 +379,7 @@ struct FeedItem {
 template <int NC, bool PM>
 struct PreSsItem {
     static constexpr int WAVES = 1;   // minimum wavefronts per SIMD
+    static constexpr bool kPerMixture = PM;   // one component set per mixture
     static constexpr uint32_t OUT = (1u << L_SA) | (1u << L_SAFIN) | (1u << L_SPLIT);   // lists the steps append to
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_PRE;
@@ -457,6 +459,7 @@ struct PreSsItem {
 template <int NC, bool PM>
 struct SaSsItem {
     static constexpr int WAVES = 1;   // minimum wavefronts per SIMD
+    static constexpr bool kPerMixture = PM;   // one component set per mixture
     static constexpr uint32_t OUT = 1u << L_SATR;   // lists the steps append to
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_SA;
@@ -561,6 +564,7 @@ struct SaSsItem {
 template <int NC, bool PM>
 struct SaTrItem {
     static constexpr int WAVES = 1;   // minimum wavefronts per SIMD
+    static constexpr bool kPerMixture = PM;   // one component set per mixture
     static constexpr uint32_t OUT = 0u;   // lists the steps append to
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_SATR;
@@ -709,6 +713,7 @@ struct SaTrItem {
 template <int NC, bool PM>
 struct SaFinItem {
     static constexpr int WAVES = 1;   // minimum wavefronts per SIMD
+    static constexpr bool kPerMixture = PM;   // one component set per mixture
     static constexpr uint32_t OUT = 1u << L_SPLIT;   // lists the steps append to
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_SAFIN;
@@ -757,6 +762,7 @@ struct SaFinItem {
 template <int NC, bool PM>
 struct SpSsItem {
     static constexpr int WAVES = (NC <= 8 ? 2 : 1);   // minimum wavefronts per SIMD
+    static constexpr bool kPerMixture = PM;   // one component set per mixture
     static constexpr uint32_t OUT = (1u << L_NT) | (1u << L_NTP);   // lists the steps append to
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_SPLIT;
@@ -889,6 +895,7 @@ struct SpSsItem {
 template <int NC, bool PM>
 struct SpNtItem {
     static constexpr int WAVES = 1;   // minimum wavefronts per SIMD
+    static constexpr bool kPerMixture = PM;   // one component set per mixture
     static constexpr uint32_t OUT = 0u;   // lists the steps append to
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = L_NT;

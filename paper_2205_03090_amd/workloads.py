@@ -187,6 +187,25 @@ def ragged_workload_vec(name: str, seed: int, n: int, nc_set=(2, 4, 6, 8, 12, 16
     return RaggedWorkload(name, n, nc_of, off, koff, z, T, P, Tc, Pc, om, kij)
 
 
+def per_mixture_workload_vec(name: str, seed: int, n: int, nc: int, alpha: float,
+                             T_range=(200.0, 600.0), P_range=(1.0e5, 2.0e7)) -> Workload:
+    """One component set per mixture, as uniform_workload(per_mixture=True), drawn
+    vectorised for large n: all Tc, then Pc, then omega (n x nc each), then the
+    strict upper k triangles (n x nc(nc-1)/2, row-major), then z, T, P."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Tc = rng.uniform(190.0, 620.0, (n, nc))
+    Pc = rng.uniform(2.0e6, 5.0e6, (n, nc))
+    om = rng.uniform(0.01, 0.5, (n, nc))
+    iu = np.triu_indices(nc, 1)
+    k = np.zeros((n, nc, nc))
+    k[:, iu[0], iu[1]] = rng.uniform(0.0, 0.15, (n, len(iu[0])))
+    k += k.transpose(0, 2, 1)
+    z = rng.dirichlet(np.full(nc, alpha), size=n)
+    T = rng.uniform(T_range[0], T_range[1], n)
+    P = rng.uniform(P_range[0], P_range[1], n)
+    return Workload(name, n, nc, np.ascontiguousarray(z), T, P, Tc, Pc, om, k, True)
+
+
 def ragged_4m_workload(n: int = 4_000_000, seed: int = SEEDS["ragged"]) -> RaggedWorkload:
     """4,000,000 mixtures, nc ~ U{2,4,6,8,12,16,20}, one component set per
     mixture, z ~ Dir(0.5 * 1), T ~ U[200,600] K, P ~ U[1e5, 2e7] Pa."""
