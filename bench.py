@@ -264,6 +264,17 @@ def main():
         rec["fwd_adjoint"] = {"value": w.n * args.steps / wall_a, "unit": "flashes/s",
                               "ms_per_step": wall_a * 1e3 / args.steps,
                               "nan_grad_frac": float(torch.isnan(bw[1]).double().mean().item())}
+    # stability analysis alone (no phase split), as used to label samples
+    st_out = api.stability(z, T, P, Tc, Pc, om, kij)
+    torch.cuda.synchronize()
+    ts0 = time.perf_counter()
+    for _ in range(args.steps):
+        st_out = api.stability(z, T, P, Tc, Pc, om, kij)
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - ts0
+    rec["stability_only"] = {"value": w.n * args.steps / wall_s, "unit": "mixtures/s",
+                             "ms_per_step": wall_s * 1e3 / args.steps,
+                             "unstable_frac": float((st_out.label == 1).double().mean().item())}
     # the same persistent flash captured once into a HIP graph and replayed
     if args.graph:
         g = torch.cuda.CUDAGraph()

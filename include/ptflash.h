@@ -146,6 +146,14 @@ typedef struct {
                              i*(i+1)/2+j) of the Hessian of G with respect to
                              the vapour mole numbers at the solution; written
                              for two-phase mixtures only */
+    double *tm;           /* n, nullable: the value that decided stability --
+                             for a mixture found unstable by the initial
+                             substitutions (status SHORTCUT), the most negative
+                             of tpd(x), tpd(y) and Delta G (Sec. 2.2.3); else
+                             the smaller final modified tangent plane distance
+                             of the two trials (eq. tm, with tm(z) = 0).  The
+                             mixture is unstable iff tm < -eps_tm.  NaN for
+                             invalid input. */
 } ptflash_result;
 
 /* Fills the defaults listed in ptflash_options. */
@@ -164,6 +172,19 @@ size_t ptflash_workspace_bytes(const ptflash_problem *prob, const ptflash_option
 int ptflash_flash(const ptflash_problem *prob, const ptflash_options *opt,
                   ptflash_result *res, void *workspace, size_t ws_bytes,
                   hipStream_t stream);
+
+/* Stability analysis alone: the initial substitutions and their triage
+ * (Sec. 2.2.3), then Michelsen's two trials (Sec. 2.2.1, Algorithm 2) for the
+ * mixtures the triage leaves undecided -- the same arithmetic as the first
+ * stages of ptflash_flash, without the phase split.  Writes label (1 =
+ * unstable: two or more phases; 0 = stable), and, when non-NULL, tm, iters
+ * (slots 0-4), status and flops; beta, x, y and factor are not written and may
+ * be NULL.  keep_factor must be 0.  The workspace is that of ptflash_flash
+ * (ptflash_workspace_bytes).  A mixture's label here equals whether
+ * ptflash_flash sends it to the phase split. */
+int ptflash_stability(const ptflash_problem *prob, const ptflash_options *opt,
+                      ptflash_result *res, void *workspace, size_t ws_bytes,
+                      hipStream_t stream);
 
 /* Adjoint of the flash by the implicit function theorem on the converged
  * equal-fugacity system r(n^V; p) = ln y + ln phi(y) - ln x - ln phi(x) = 0,

@@ -28,7 +28,7 @@ class OrcOpts(C.Structure):
 
 
 INFO_FIELDS = ["case", "pre", "ss_v", "nt_v", "ss_l", "nt_l", "ss_split",
-               "nt_split", "flags", "out_v", "out_l", "swap", "split_ss_conv"]
+               "nt_split", "flags", "out_v", "out_l", "swap", "split_ss_conv", "unstable"]
 FLAG_INVALID, FLAG_SA_UNCONV, FLAG_SPLIT_UNCONV = 1, 2, 4
 FLAG_SPLIT_TRIVIAL, FLAG_SPLIT_FAILED, FLAG_RR_NO_ROOT = 8, 16, 32
 
@@ -61,7 +61,7 @@ def lib():
             L.orc_flash_jacobian.restype = C.c_int
             L.orc_flash_batch.argtypes = [C.c_int64, C.c_int32, _D, _D, _D, _D, _D, _D, _D,
                                           C.c_int32, C.POINTER(OrcOpts), C.c_void_p, _D, _D,
-                                          _D, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64]
+                                          _D, C.c_void_p, _D, C.c_void_p, C.c_int64, C.c_int64]
             _lib = L
     return _lib
 
@@ -130,7 +130,9 @@ def flash(w, opts: OrcOpts | None = None, threads: int | None = None, **kw):
     """Runs the oracle flash over a workload (``workloads.Workload``).
 
     Returns a dict of NumPy arrays: label (int8), beta, x, y, min_tpd (NaN
-    unless requested) and info (n x 12 int32, see INFO_FIELDS)."""
+    unless requested), tm (the value that decided stability: the most
+    negative triage value of a case-3 mixture, else the smaller final tm of
+    the two trials; NaN for invalid input) and info (see INFO_FIELDS)."""
     o = opts if opts is not None else default_opts(**kw)
     L = lib()
     n, nc = w.n, w.nc
@@ -141,6 +143,7 @@ def flash(w, opts: OrcOpts | None = None, threads: int | None = None, **kw):
     x = np.zeros((n, nc))
     y = np.zeros((n, nc))
     mtpd = np.full(n, np.nan)
+    tmd = np.full(n, np.nan)
     info = np.zeros((n, L.orc_ninfo()), np.int32)
     threads = threads or 1
     bounds = np.linspace(0, n, threads + 1).astype(np.int64)
@@ -148,7 +151,7 @@ def flash(w, opts: OrcOpts | None = None, threads: int | None = None, **kw):
     def run(k):
         L.orc_flash_batch(n, nc, _p(z), _p(T), _p(P), _p(Tc), _p(Pc), _p(om), _p(kk),
                           int(w.per_mixture), C.byref(o), label.ctypes.data, _p(beta),
-                          _p(x), _p(y), mtpd.ctypes.data, info.ctypes.data,
+                          _p(x), _p(y), mtpd.ctypes.data, _p(tmd), info.ctypes.data,
                           int(bounds[k]), int(bounds[k + 1]))
 
     if threads == 1:
@@ -156,7 +159,7 @@ def flash(w, opts: OrcOpts | None = None, threads: int | None = None, **kw):
     else:
         with ThreadPoolExecutor(threads) as ex:
             list(ex.map(run, range(threads)))
-    return dict(label=label, beta=beta, x=x, y=y, min_tpd=mtpd, info=info)
+    return dict(label=label, beta=beta, x=x, y=y, min_tpd=mtpd, tm=tmd, info=info)
 
 
 def flash_jacobian(Tc, Pc, omega, kij, z, T, P, beta, y, hrel=1e-3):

@@ -106,7 +106,7 @@ typedef struct {
 enum {
     ORC_I_CASE = 0, ORC_I_PRE, ORC_I_SS_V, ORC_I_NT_V, ORC_I_SS_L, ORC_I_NT_L,
     ORC_I_SS_SPLIT, ORC_I_NT_SPLIT, ORC_I_FLAGS, ORC_I_OUT_V, ORC_I_OUT_L,
-    ORC_I_NROOT_SWAP, ORC_I_SPLIT_SS_CONV, ORC_NINFO
+    ORC_I_NROOT_SWAP, ORC_I_SPLIT_SS_CONV, ORC_I_UNSTABLE, ORC_NINFO
 };
 
 /* ---------------------------------------------------------------------- */
@@ -771,6 +771,7 @@ static int orc_split_newton(const orc_eos *e, const double *z, double *nV,
 typedef struct {
     int label;
     double beta, min_tpd;
+    double tm_dec;   /* the value that decided stability (see orc_flash_one) */
     double x[ORC_NCMAX], y[ORC_NCMAX];
     int32_t info[ORC_NINFO];
 } orc_result;
@@ -796,6 +797,7 @@ int orc_flash_one(int nc, const double *z_in, double T, double P,
 {
     memset(res, 0, sizeof(*res));
     res->min_tpd = NAN;
+    res->tm_dec = NAN;
     orc_single_phase(nc, z_in, res);
     res->info[ORC_I_FLAGS] = ORC_INVALID;
     if (nc < 1 || nc > ORC_NCMAX || !(T > 0.0) || !(P > 0.0) || !isfinite(T) || !isfinite(P))
@@ -855,6 +857,9 @@ int orc_flash_one(int nc, const double *z_in, double T, double P,
     }
     res->info[ORC_I_CASE] = kase;
     res->info[ORC_I_PRE] = npre;
+    /* the decisive value of a case-3 mixture: the most negative of the
+     * triage's tpd(x), tpd(y) and Delta G */
+    if (kase == 3) res->tm_dec = fmin(tpdx, fmin(tpdy, (1.0 - th) * tpdx + th * tpdy));
 
     /* Stability analysis (Sec. 2.2.1, Algorithm 2): vapour-like W = K z and
      * liquid-like W = z / K from the Wilson K (R5), each by successive
@@ -876,6 +881,8 @@ int orc_flash_one(int nc, const double *z_in, double T, double P,
             res->info[t == 0 ? ORC_I_OUT_V : ORC_I_OUT_L] = out;
         }
         unstable = (tmt[0] < -o->eps_tm) || (tmt[1] < -o->eps_tm);
+        /* the decisive value after stability analysis: the smaller final tm */
+        res->tm_dec = fmin(tmt[0], tmt[1]);
         if (unstable) {
             /* K re-estimate (Sec. 2.2.1, last paragraph) */
             if (tmt[1] < tmt[0])
@@ -910,6 +917,7 @@ int orc_flash_one(int nc, const double *z_in, double T, double P,
         res->min_tpd = mt;
     }
 
+    res->info[ORC_I_UNSTABLE] = unstable;
     if (!unstable) {
         res->info[ORC_I_FLAGS] = (int32_t)flags;
         return 0;
@@ -996,13 +1004,13 @@ int orc_ncmax(void) { return ORC_NCMAX; }
 
 /* Batch driver over rows [begin, end).  props_per_mixture = 0: Tc, Pc, omega
  * hold nc values and kij nc*nc, shared by every mixture; 1: they hold n*nc
- * and n*nc*nc values, one set per mixture.  label/beta/x/y/min_tpd/info are
- * full-size arrays indexed by mixture (min_tpd may be NULL). */
+ * and n*nc*nc values, one set per mixture.  label/beta/x/y/min_tpd/tm/info are
+ * full-size arrays indexed by mixture (min_tpd and tm may be NULL). */
 void orc_flash_batch(int64_t n, int32_t nc, const double *z, const double *T,
                      const double *P, const double *Tc, const double *Pc,
                      const double *omega, const double *kij, int32_t props_per_mixture,
                      const orc_opts *o, int8_t *label, double *beta, double *x,
-                     double *y, double *min_tpd, int32_t *info, int64_t begin,
+                     double *y, double *min_tpd, double *tm, int32_t *info, int64_t begin,
                      int64_t end)
 {
     (void)n;
@@ -1017,6 +1025,7 @@ void orc_flash_batch(int64_t n, int32_t nc, const double *z, const double *T,
         beta[m] = r.beta;
         for (int i = 0; i < nc; ++i) { x[m * nc + i] = r.x[i]; y[m * nc + i] = r.y[i]; }
         if (min_tpd) min_tpd[m] = r.min_tpd;
+        if (tm) tm[m] = r.tm_dec;
         if (info) memcpy(info + m * ORC_NINFO, r.info, sizeof(int32_t) * ORC_NINFO);
     }
 }

@@ -19,7 +19,7 @@ ST = dict(INVALID=0x0001, SHORTCUT=0x0002, SA_RAN=0x0004, SA_UNCONV=0x0008,
 EXPORTS = ["ptflash_default_options", "ptflash_max_nc", "ptflash_workspace_bytes",
            "ptflash_flash", "ptflash_flash_backward", "ptflash_backward_workspace_bytes",
            "ptflash_eval_phase", "ptflash_strerror", "ptflash_ragged_workspace_bytes",
-           "ptflash_flash_ragged"]
+           "ptflash_flash_ragged", "ptflash_stability"]
 
 _vp = C.c_void_p
 
@@ -49,7 +49,7 @@ class Options(C.Structure):
 
 class Result(C.Structure):
     _fields_ = [("label", _vp), ("beta", _vp), ("x", _vp), ("y", _vp), ("iters", _vp),
-                ("status", _vp), ("flops", _vp), ("factor", _vp)]
+                ("status", _vp), ("flops", _vp), ("factor", _vp), ("tm", _vp)]
 
 
 _lib = None
@@ -71,6 +71,8 @@ def lib():
         L.ptflash_flash.argtypes = [C.POINTER(Problem), C.POINTER(Options), C.POINTER(Result),
                                     _vp, C.c_size_t, _vp]
         L.ptflash_flash.restype = C.c_int
+        L.ptflash_stability.argtypes = L.ptflash_flash.argtypes
+        L.ptflash_stability.restype = C.c_int
         L.ptflash_backward_workspace_bytes.argtypes = [C.POINTER(Problem), C.c_int32]
         L.ptflash_backward_workspace_bytes.restype = C.c_size_t
         L.ptflash_flash_backward.argtypes = [C.POINTER(Problem), C.POINTER(Options),

@@ -23,6 +23,7 @@ class FlashResult:
     status: torch.Tensor    # (n,) int16 status bits (see _capi.ST)
     flops: torch.Tensor     # (n,) int32 algorithmic flops per mixture
     factor: torch.Tensor | None  # (n, nc(nc+1)/2) Cholesky factor or None
+    tm: torch.Tensor | None = None  # (n,) float64 value that decided stability
 
 
 def _ptr(t: torch.Tensor | None):
@@ -76,11 +77,13 @@ def flash(z, T, P, Tc, Pc, omega, kij, *, keep_factor: bool = False, stream=None
             status=torch.empty(n, dtype=torch.int16, device=dev),
             flops=torch.empty(n, dtype=torch.int32, device=dev),
             factor=(torch.full((n, nc * (nc + 1) // 2), float("nan"), dtype=torch.float64,
-                               device=dev) if keep_factor else None))
+                               device=dev) if keep_factor else None),
+            tm=torch.empty(n, dtype=torch.float64, device=dev))
     res = _capi.Result(label=_ptr(out.label).value, beta=_ptr(out.beta).value,
                        x=_ptr(out.x).value, y=_ptr(out.y).value, iters=_ptr(out.iters).value,
                        status=_ptr(out.status).value, flops=_ptr(out.flops).value,
-                       factor=None if out.factor is None else _ptr(out.factor).value)
+                       factor=None if out.factor is None else _ptr(out.factor).value,
+                       tm=None if out.tm is None else _ptr(out.tm).value)
     L = _capi.lib()
     ws_bytes = L.ptflash_workspace_bytes(C.byref(prob), C.byref(o))
     ws = _workspace(ws_bytes, dev)
@@ -88,6 +91,33 @@ def flash(z, T, P, Tc, Pc, omega, kij, *, keep_factor: bool = False, stream=None
                          _stream_handle(stream))
     _capi.check(rc, "ptflash_flash")
     out._keepalive = (z, T, P, Tc, Pc, omega, kij, ws)  # until the stream is done
+    return out
+
+
+def stability(z, T, P, Tc, Pc, omega, kij, *, stream=None, **opts) -> FlashResult:
+    """Stability analysis alone (ptflash_stability): label (1 = unstable), tm
+    (the value that decided it), iters, status and flops; beta, x, y are None."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    z, T, P = _f64(z, dev), _f64(T, dev), _f64(P, dev)
+    Tc, Pc, omega, kij = (_f64(a, dev) for a in (Tc, Pc, omega, kij))
+    n, nc = z.shape
+    o = _capi.default_options(**opts)
+    prob = make_problem(z, T, P, Tc, Pc, omega, kij)
+    out = FlashResult(label=torch.empty(n, dtype=torch.int8, device=dev), beta=None, x=None,
+                      y=None, iters=torch.empty((n, _capi.NITERS), dtype=torch.int16, device=dev),
+                      status=torch.empty(n, dtype=torch.int16, device=dev),
+                      flops=torch.empty(n, dtype=torch.int32, device=dev), factor=None,
+                      tm=torch.empty(n, dtype=torch.float64, device=dev))
+    res = _capi.Result(label=_ptr(out.label).value, beta=None, x=None, y=None,
+                       iters=_ptr(out.iters).value, status=_ptr(out.status).value,
+                       flops=_ptr(out.flops).value, factor=None, tm=_ptr(out.tm).value)
+    L = _capi.lib()
+    ws_bytes = L.ptflash_workspace_bytes(C.byref(prob), C.byref(o))
+    ws = _workspace(ws_bytes, dev)
+    rc = L.ptflash_stability(C.byref(prob), C.byref(o), C.byref(res), _ptr(ws), ws_bytes,
+                             _stream_handle(stream))
+    _capi.check(rc, "ptflash_stability")
+    out._keepalive = (z, T, P, Tc, Pc, omega, kij, ws)
     return out
 
 
@@ -116,10 +146,11 @@ def flash_ragged(z, T, P, nc_of, off, koff, Tc, Pc, omega, kij, *, stream=None, 
         iters=torch.empty((n, _capi.NITERS), dtype=torch.int16, device=dev),
         status=torch.empty(n, dtype=torch.int16, device=dev),
         flops=torch.empty(n, dtype=torch.int32, device=dev),
-        factor=None)
+        factor=None, tm=torch.empty(n, dtype=torch.float64, device=dev))
     res = _capi.Result(label=_ptr(out.label).value, beta=_ptr(out.beta).value,
                        x=_ptr(out.x).value, y=_ptr(out.y).value, iters=_ptr(out.iters).value,
-                       status=_ptr(out.status).value, flops=_ptr(out.flops).value, factor=None)
+                       status=_ptr(out.status).value, flops=_ptr(out.flops).value, factor=None,
+                       tm=_ptr(out.tm).value)
     L = _capi.lib()
     ws_bytes = L.ptflash_ragged_workspace_bytes(C.byref(prob), C.byref(o))
     ws = _workspace(ws_bytes, dev)

@@ -28,6 +28,8 @@ struct FlashArgs {
     uint16_t *status;
     uint32_t *flops;
     double *factor;
+    double *tm;            // nullable: the value that decided stability
+    int stability_only;    // stop after the stability decision (no split)
 };
 
 // Arguments of the backward kernel.

@@ -669,6 +669,7 @@ int launch_persistent(const FlashArgs &a, const ptflash_problem *p, const ptflas
     if ((rc = run_persistent_stage<SaSsItem<NC, PM>, NC>(c, p, o, kTake0 + 2, s))) return rc;
     if ((rc = run_tr_stage<SaTrItem, SaTrGroup, NC, PM>(c, p, o, lsa, kTake0 + 3, s))) return rc;
     if ((rc = run_persistent_stage<SaFinItem<NC, PM>, NC>(c, p, o, kTake0 + 4, s))) return rc;
+    if (a.stability_only) return PTFLASH_OK;
     if ((rc = run_persistent_stage<SpSsItem<NC, PM>, NC>(c, p, o, kTake0 + 5, s))) return rc;
     if ((rc = run_tr_stage<SpNtItem, SpNtGroup, NC, PM>(c, p, o, lsp, kTake0 + 6, s))) return rc;
     return PTFLASH_OK;
@@ -734,6 +735,7 @@ int launch_plain(const FlashArgs &a, const ptflash_problem *p, void *ws, hipStre
     if ((rc = run_plain_stage<SaSsItem<NC, PM>, NC>(c, p, tail, s))) return rc;
     if ((rc = run_plain_stage<SaTrItem<NC, PM>, NC>(c, p, tail, s))) return rc;
     if ((rc = run_plain_stage<SaFinItem<NC, PM>, NC>(c, p, tail, s))) return rc;
+    if (a.stability_only) return PTFLASH_OK;
     if ((rc = run_plain_stage<SpSsItem<NC, PM>, NC>(c, p, tail, s))) return rc;
     if ((rc = run_plain_stage<SpNtItem<NC, PM>, NC>(c, p, tail, s))) return rc;
     return PTFLASH_OK;

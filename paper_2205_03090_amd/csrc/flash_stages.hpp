@@ -181,11 +181,13 @@ __device__ __forceinline__ void write_outputs_single(const Ctx<NC> &c, int64_t m
 {
     const FlashArgs &a = c.a;
     a.label[m] = 0;
-    a.beta[m] = -1.0;
+    if (a.beta) a.beta[m] = -1.0;
+    if (a.x) {
 #pragma unroll
-    for (int i = 0; i < NC; ++i) {
-        a.x[m * NC + i] = z[i];
-        a.y[m * NC + i] = z[i];
+        for (int i = 0; i < NC; ++i) {
+            a.x[m * NC + i] = z[i];
+            a.y[m * NC + i] = z[i];
+        }
     }
     if (a.iters) {
 #pragma unroll
@@ -200,6 +202,23 @@ __device__ __forceinline__ void load_it(int16_t (&it)[8], const MixRec<NC> &r)
 {
 #pragma unroll
     for (int k = 0; k < 8; ++k) it[k] = r.it[k];
+}
+
+// Outputs of a mixture found unstable when only the stability decision is
+// asked for (no phase split): label 1 and the counters.
+template <int NC>
+__device__ __forceinline__ void write_outputs_unstable(const Ctx<NC> &c, int64_t m,
+                                                       uint32_t status, uint32_t fl,
+                                                       const int16_t (&it)[8])
+{
+    const FlashArgs &a = c.a;
+    a.label[m] = 1;
+    if (a.iters) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) a.iters[m * 8 + k] = it[k];
+    }
+    if (a.status) a.status[m] = (uint16_t)status;
+    if (a.flops) a.flops[m] = fl;
 }
 
 // K -> Rachford-Rice -> normalised x, y (x_i = z_i/(1 + th(K_i - 1)),
@@ -330,6 +349,7 @@ struct FeedItem {
             // invalid input: report the raw feed as a single phase
             int16_t it[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             write_outputs_single<NC>(c, m, z, kStInvalid, 0, it);
+            if (c.a.tm) c.a.tm[m] = NAN;
             return false;
         }
 #pragma unroll
@@ -444,9 +464,16 @@ struct PreSsItem {
         }
         const double dg = (1.0 - theta) * tx + theta * ty;
         fl += 8 * NC + 3;
-        if (tx < -a.eps_tm || ty < -a.eps_tm || dg < -a.eps_tm)
+        if (tx < -a.eps_tm || ty < -a.eps_tm || dg < -a.eps_tm) {
+            // case 3: unstable; the decisive value is the most negative one
+            if (a.tm) a.tm[m] = fmin(tx, fmin(ty, dg));
+            if (a.stability_only) {
+                int16_t it[8] = {(int16_t)npre, 0, 0, 0, 0, 0, 0, 0};
+                write_outputs_unstable<NC>(c, m, kStShortcut, fl, it);
+                return true;
+            }
             route_mixture<NC>(r, ob, m, true, kStShortcut, fl, npre, lk, 0.5);
-        else
+        } else
             route_mixture<NC>(r, ob, m, false, kStSaRan, fl, npre, lk, theta);
         return true;
     }
@@ -733,6 +760,13 @@ struct SaFinItem {
         const uint32_t status = r.status | r.tst[0] | r.tst[1];
         uint32_t fl = r.fl + r.tfl[0] + r.tfl[1];
         const bool unstable = (t0 < -c.a.eps_tm) || (t1 < -c.a.eps_tm);
+        if (c.a.tm) c.a.tm[m] = fmin(t0, t1);
+        if (unstable && c.a.stability_only) {
+            int16_t it[8];
+            load_it<NC>(it, r);
+            write_outputs_unstable<NC>(c, m, status, fl, it);
+            return true;
+        }
         if (!unstable) {
             double z[NC];
             load_z<NC>(z, c.a, m);

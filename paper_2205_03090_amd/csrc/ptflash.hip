@@ -95,6 +95,8 @@ static void fill_args(FlashArgs &a, const ptflash_problem *p, const ptflash_opti
     a.status = r->status;
     a.flops = r->flops;
     a.factor = r->factor;
+    a.tm = r->tm;
+    a.stability_only = 0;
 }
 
 // Compile-time dispatch over the component count.
@@ -210,7 +212,7 @@ struct RaggedIn {
 struct Uniform {   // one gathered uniform-nc chunk
     double *z, *T, *P, *Tc, *Pc, *om, *K;
     int8_t *label;
-    double *beta, *x, *y;
+    double *beta, *x, *y, *tm;
     int16_t *iters;
     uint16_t *status;
     uint32_t *flops;
@@ -274,6 +276,7 @@ ragged_scatter_rows(int64_t cnt, const uint32_t *__restrict__ ids, const int64_t
                 r.iters[m * PTFLASH_NITERS + k] = u.iters[j * PTFLASH_NITERS + k];
         if (r.status) r.status[m] = u.status[j];
         if (r.flops) r.flops[m] = u.flops[j];
+        if (r.tm) r.tm[m] = u.tm[j];
     }
 }
 
@@ -322,6 +325,7 @@ ragged_invalid(int64_t cnt, const uint32_t *__restrict__ ids, const int64_t *off
         for (int k = 0; k < PTFLASH_NITERS; ++k) r.iters[m * PTFLASH_NITERS + k] = 0;
     if (r.status) r.status[m] = (uint16_t)PTFLASH_ST_INVALID;
     if (r.flops) r.flops[m] = 0u;
+    if (r.tm) r.tm[m] = NAN;
 }
 
 __global__ void zero_u64(unsigned long long *q, int n)
@@ -344,7 +348,8 @@ static size_t ragged_ws_layout(int64_t n, int form, size_t *flash_off)
     size_t b = align256(2 * kBuckets * sizeof(unsigned long long));
     b += align256((size_t)n * 4);
     b += align256(ch * C * 8) * 6 + align256(ch * C * C * 8) + align256(ch * 8) * 3 +
-         align256(ch) + align256(ch * PTFLASH_NITERS * 2) + align256(ch * 2) + align256(ch * 4);
+         align256(ch) + align256(ch * PTFLASH_NITERS * 2) + align256(ch * 2) + align256(ch * 4) +
+         align256(ch * 8);
     *flash_off = b;
     size_t fw = 0;
     if (Dispatch<WsF>::run(kMaxNc, (int64_t)ch, form, &fw) != PTFLASH_OK) return 0;
@@ -425,6 +430,27 @@ int ptflash_flash(const ptflash_problem *p, const ptflash_options *o, ptflash_re
     if (((uintptr_t)ws & 255u) != 0) return PTFLASH_EINVAL;
     FlashArgs a;
     fill_args(a, p, o, r);
+    return Dispatch<FlashF>::run(p->nc, a, p, o, ws, s);
+}
+
+int ptflash_stability(const ptflash_problem *p, const ptflash_options *o, ptflash_result *r,
+                      void *ws, size_t ws_bytes, hipStream_t s)
+{
+    if (!problem_ok(p) || !options_ok(o) || !r) return PTFLASH_EINVAL;
+    if (p->nc < kMinNc || p->nc > kMaxNc) return PTFLASH_EUNSUPPORTED;
+    if (p->props_per_mixture != 0 && p->props_per_mixture != 1) return PTFLASH_EINVAL;
+    if (p->n == 0) return PTFLASH_OK;
+    if (p->n > (int64_t)1 << 30) return PTFLASH_EUNSUPPORTED;
+    if (!r->label || o->keep_factor) return PTFLASH_EINVAL;
+    if (!ws || ws_bytes < ptflash_workspace_bytes(p, o)) return PTFLASH_EWORKSPACE;
+    if (((uintptr_t)ws & 255u) != 0) return PTFLASH_EINVAL;
+    FlashArgs a;
+    fill_args(a, p, o, r);
+    a.beta = nullptr;
+    a.x = nullptr;
+    a.y = nullptr;
+    a.factor = nullptr;
+    a.stability_only = 1;
     return Dispatch<FlashF>::run(p->nc, a, p, o, ws, s);
 }
 
@@ -548,6 +574,7 @@ int ptflash_flash_ragged(const ptflash_ragged_problem *p, const ptflash_options 
     u.iters = (int16_t *)takeb(ch * PTFLASH_NITERS * 2);
     u.status = (uint16_t *)takeb(ch * 2);
     u.flops = (uint32_t *)takeb(ch * 4);
+    u.tm = (double *)takeb(ch * 8);
     void *fws = (char *)ws + foff;
     const size_t fws_bytes = ws_bytes - foff;
 
@@ -579,7 +606,8 @@ int ptflash_flash_ragged(const ptflash_ragged_problem *p, const ptflash_options 
             const uint32_t *cid = ids + st.s[nc] + c0;
             RaggedMove<kMinNc>::run(nc, true, cnt, cid, in, u, p->off, rr, s);
             ptflash_problem sub{cnt, nc, 1, u.z, u.T, u.P, u.Tc, u.Pc, u.om, u.K};
-            ptflash_result sr{u.label, u.beta, u.x, u.y, u.iters, u.status, u.flops, nullptr};
+            ptflash_result sr{u.label, u.beta, u.x, u.y, u.iters, u.status, u.flops, nullptr,
+                              r->tm ? u.tm : nullptr};
             if (fws_bytes < ptflash_workspace_bytes(&sub, o)) return PTFLASH_EWORKSPACE;
             FlashArgs a;
             fill_args(a, &sub, o, &sr);

@@ -54,6 +54,8 @@ def gpu_to_numpy(r):
            ("label", "beta", "x", "y", "iters", "status", "flops")}
     if r.factor is not None:
         out["factor"] = r.factor.detach().cpu().numpy()
+    if getattr(r, "tm", None) is not None:
+        out["tm"] = r.tm.detach().cpu().numpy()
     return out
 
 
