@@ -96,3 +96,29 @@ def test_table5_stage_shares_gpu():
     assert it[:, IT["pre"]].max() <= 3
     assert max(it[:, IT["ss_v"]].max(), it[:, IT["ss_l"]].max(), it[:, IT["ss_split"]].max()) <= 9
     assert max(mx.values()) <= 20
+
+
+def test_split_convergence_diagnostics_follow_fig5():
+    # Sec. 5.1 / Fig. 5 on the nine-component case at n = 1e6: most
+    # trust-region splits finish within 3 steps (92.67 % in the paper), and
+    # the mixtures that need more steps are closer to a critical point (the
+    # mean critical distance d_c falls from the substitution-settled ones to
+    # the trust-region ones and with the step count)
+    from paper_2205_03090_amd import diagnostics
+    w = workloads.case_study_workload("cs9", 1_000_000)
+    print("case cs9 split convergence n=1e6", flush=True)
+    g = _run(w)
+    d = diagnostics.split_convergence(g["label"], g["x"], g["y"], g["iters"], g["status"])
+    print(f"[cs9 fig5] two-phase {d['n_two_phase']}, trust region {d['n_trust_region']}, "
+          f"settled within 3 steps {d['tr_settled_share'][2]:.4f}, mean d_c "
+          f"{ {k: round(v, 3) for k, v in d['mean_dc'].items()} }, "
+          f"counts {d['count']}", flush=True)
+    assert d["tr_settled_share"][2] > 0.85
+    assert np.all(np.diff(d["tr_settled_share"]) >= 0) and d["tr_settled_share"][-1] == 1.0
+    dc = d["mean_dc"]
+    assert dc["ss"] > dc["1"] > dc["3"]
+    # with enough mixtures per step count, d_c falls with the step count
+    ks = [int(k) for k in dc if k != "ss" and d["count"][k] >= 200]
+    vals = [dc[str(k)] for k in sorted(ks)]
+    rho = np.corrcoef(sorted(ks), vals)[0, 1]
+    assert rho < -0.5, (ks, vals)
