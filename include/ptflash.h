@@ -63,6 +63,7 @@ extern "C" {
 #define PTFLASH_ST_RR_NO_ROOT     0x0100u /* all K on one side of 1 in the split */
 #define PTFLASH_ST_SWAPPED        0x0200u /* phases re-labelled so that Z_y > Z_x */
 #define PTFLASH_ST_STEP_CAP       0x0400u /* stopped by the per-mixture step cap */
+#define PTFLASH_ST_HINTED         0x0800u /* label set by the caller's hint */
 
 /* ---- iteration counters (iters[m*PTFLASH_NITERS + k]) ---- */
 #define PTFLASH_IT_PRE 0        /* initial phase-split substitutions (<= 3)  */
@@ -97,6 +98,21 @@ typedef struct {
     const double *Pc;     /* nc or n*nc      */
     const double *omega;  /* nc or n*nc      */
     const double *kij;    /* nc*nc or n*nc*nc */
+    /* Optional per-mixture inputs (NULL: none).  They are where an external
+     * initializer or classifier (the paper's neural networks, Sec. 4) or the
+     * result of a previous time step enters the flash. */
+    const double *lnk0;   /* n*nc: initial ln K in place of Wilson's (eq.
+                             wilson), wherever the flash uses it: the first
+                             substitutions, the two stability trials
+                             W = K z and W = z / K, and the split of a
+                             hinted-unstable mixture (Sec. 4: the
+                             initializer serves stability analysis and split).
+                             A row with a non-finite value is INVALID. */
+    const int8_t *hint;   /* n: 0 = known stable (single phase, no analysis),
+                             1 = known unstable (the split starts at once from
+                             lnk0, else Wilson's K, without the triage and
+                             the stability analysis); other values: none.
+                             Hinted mixtures carry status HINTED and tm NaN. */
 } ptflash_problem;
 
 /* Options; ptflash_default_options() fills the paper's values. */

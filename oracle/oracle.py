@@ -31,6 +31,7 @@ INFO_FIELDS = ["case", "pre", "ss_v", "nt_v", "ss_l", "nt_l", "ss_split",
                "nt_split", "flags", "out_v", "out_l", "swap", "split_ss_conv", "unstable"]
 FLAG_INVALID, FLAG_SA_UNCONV, FLAG_SPLIT_UNCONV = 1, 2, 4
 FLAG_SPLIT_TRIVIAL, FLAG_SPLIT_FAILED, FLAG_RR_NO_ROOT = 8, 16, 32
+FLAG_HINTED = 64
 
 _D = C.POINTER(C.c_double)
 
@@ -60,7 +61,8 @@ def lib():
                                              _D, C.c_double, _D, C.c_double, _D]
             L.orc_flash_jacobian.restype = C.c_int
             L.orc_flash_batch.argtypes = [C.c_int64, C.c_int32, _D, _D, _D, _D, _D, _D, _D,
-                                          C.c_int32, C.POINTER(OrcOpts), C.c_void_p, _D, _D,
+                                          C.c_int32, _D, C.c_void_p, C.POINTER(OrcOpts),
+                                          C.c_void_p, _D, _D,
                                           _D, C.c_void_p, _D, C.c_void_p, C.c_int64, C.c_int64]
             _lib = L
     return _lib
@@ -126,8 +128,13 @@ def split_residual(Tc, Pc, omega, kij, T, P, z, nV):
     return r, G
 
 
-def flash(w, opts: OrcOpts | None = None, threads: int | None = None, **kw):
+def flash(w, opts: OrcOpts | None = None, threads: int | None = None, lnk0=None, hint=None,
+          **kw):
     """Runs the oracle flash over a workload (``workloads.Workload``).
+
+    lnk0 (n x nc, optional): initial ln K in place of Wilson's (substitutions
+    and stability trials); hint (n, int8, optional): 0 = known stable, 1 = known
+    unstable (case 4 in info: the split starts at once), other values none.
 
     Returns a dict of NumPy arrays: label (int8), beta, x, y, min_tpd (NaN
     unless requested), tm (the value that decided stability: the most
@@ -145,12 +152,16 @@ def flash(w, opts: OrcOpts | None = None, threads: int | None = None, **kw):
     mtpd = np.full(n, np.nan)
     tmd = np.full(n, np.nan)
     info = np.zeros((n, L.orc_ninfo()), np.int32)
+    lk = None if lnk0 is None else _f64(np.asarray(lnk0).reshape(n, nc))
+    hn = None if hint is None else np.ascontiguousarray(np.asarray(hint, dtype=np.int8).reshape(n))
     threads = threads or 1
     bounds = np.linspace(0, n, threads + 1).astype(np.int64)
 
     def run(k):
         L.orc_flash_batch(n, nc, _p(z), _p(T), _p(P), _p(Tc), _p(Pc), _p(om), _p(kk),
-                          int(w.per_mixture), C.byref(o), label.ctypes.data, _p(beta),
+                          int(w.per_mixture), _p(lk) if lk is not None else None,
+                          hn.ctypes.data if hn is not None else None, C.byref(o),
+                          label.ctypes.data, _p(beta),
                           _p(x), _p(y), mtpd.ctypes.data, _p(tmd), info.ctypes.data,
                           int(bounds[k]), int(bounds[k + 1]))
 

@@ -101,6 +101,7 @@ typedef struct {
 #define ORC_SPLIT_TRIVIAL  8u
 #define ORC_SPLIT_FAILED  16u
 #define ORC_RR_NO_ROOT    32u
+#define ORC_HINTED        64u
 
 /* info[] layout per mixture */
 enum {
@@ -791,9 +792,15 @@ static void orc_single_phase(int nc, const double *z, orc_result *res)
     for (int i = 0; i < nc; ++i) { res->x[i] = z[i]; res->y[i] = z[i]; }
 }
 
+/* lnk0 (nullable): the caller's initial ln K in place of Wilson's, wherever
+ * the flash uses Wilson's (the first substitutions, the two stability trials
+ * and the split of a hinted-unstable mixture; Sec. 4).  hint: 0 = known stable (single phase, no analysis), 1 =
+ * known unstable (the split starts from the initial K without the triage and
+ * the stability analysis; case 4 in info), other values: none. */
 int orc_flash_one(int nc, const double *z_in, double T, double P,
                   const double *Tc, const double *Pc, const double *omega,
-                  const double *kij, const orc_opts *o, orc_result *res)
+                  const double *kij, const double *lnk0, int hint, const orc_opts *o,
+                  orc_result *res)
 {
     memset(res, 0, sizeof(*res));
     res->min_tpd = NAN;
@@ -811,9 +818,17 @@ int orc_flash_one(int nc, const double *z_in, double T, double P,
         for (int j = 0; j < nc; ++j)
             if (kij[i * nc + j] != kij[j * nc + i] || (i == j && kij[i * nc + i] != 0.0))
                 return ORC_INVALID;
+        if (lnk0 && !isfinite(lnk0[i])) return ORC_INVALID;
     }
     res->info[ORC_I_FLAGS] = 0;
     unsigned flags = 0;
+    if (hint == 0) {
+        double zn[ORC_NCMAX];
+        for (int i = 0; i < nc; ++i) zn[i] = z_in[i] / zs;
+        orc_single_phase(nc, zn, res);
+        res->info[ORC_I_FLAGS] = ORC_HINTED;
+        return 0;
+    }
 
     double z[ORC_NCMAX], lnz[ORC_NCMAX];
     for (int i = 0; i < nc; ++i) { z[i] = z_in[i] / zs; lnz[i] = log(z[i]); }
@@ -828,7 +843,8 @@ int orc_flash_one(int nc, const double *z_in, double T, double P,
     for (int i = 0; i < nc; ++i) d[i] = lnz[i] + lpz[i];
 
     double lnKw[ORC_NCMAX], lnK[ORC_NCMAX], K[ORC_NCMAX];
-    orc_wilson(nc, Tc, Pc, omega, T, P, lnKw);
+    if (lnk0) memcpy(lnKw, lnk0, sizeof(double) * nc);
+    else orc_wilson(nc, Tc, Pc, omega, T, P, lnKw);
     memcpy(lnK, lnKw, sizeof(double) * nc);
 
     /* Three initial substitutions of the phase split and the triage (Sec.
@@ -837,7 +853,11 @@ int orc_flash_one(int nc, const double *z_in, double T, double P,
     int kase = 0, npre = 0;
     double th = 0.0, x[ORC_NCMAX], y[ORC_NCMAX], lx[ORC_NCMAX], ly[ORC_NCMAX];
     double tpdx = INFINITY, tpdy = INFINITY;
-    for (int k = 1; k <= o->max_pre_ss; ++k) {
+    if (hint == 1) {
+        kase = 4;   /* the caller's hint: unstable, no triage */
+        flags |= ORC_HINTED;
+    }
+    for (int k = 1; kase != 4 && k <= o->max_pre_ss; ++k) {
         for (int i = 0; i < nc; ++i) K[i] = exp(lnK[i]);
         if (orc_rr_solve(nc, z, K, &th) != 0 || !(th > 0.0 && th < 1.0)) { kase = 1; break; }
         orc_xy_from_k(nc, z, K, th, x, y);
@@ -846,7 +866,7 @@ int orc_flash_one(int nc, const double *z_in, double T, double P,
         for (int i = 0; i < nc; ++i) lnK[i] = lx[i] - ly[i];
         npre = k;
     }
-    if (kase != 1) {
+    if (kase != 1 && kase != 4) {
         tpdx = 0.0; tpdy = 0.0;
         for (int i = 0; i < nc; ++i) {
             tpdx += x[i] * (log(x[i]) + lx[i] - d[i]);
@@ -866,8 +886,8 @@ int orc_flash_one(int nc, const double *z_in, double T, double P,
      * substitution, then the second-order stand-in when not stopped. */
     double lnWt[2][ORC_NCMAX], tmt[2] = {INFINITY, INFINITY};
     int ran_sa = 0;
-    int unstable = (kase == 3);
-    if (kase != 3) {
+    int unstable = (kase == 3 || kase == 4);
+    if (kase == 1 || kase == 2) {
         ran_sa = 1;
         for (int t = 0; t < 2; ++t) {
             for (int i = 0; i < nc; ++i) lnWt[t][i] = lnz[i] + (t == 0 ? lnKw[i] : -lnKw[i]);
@@ -1009,6 +1029,7 @@ int orc_ncmax(void) { return ORC_NCMAX; }
 void orc_flash_batch(int64_t n, int32_t nc, const double *z, const double *T,
                      const double *P, const double *Tc, const double *Pc,
                      const double *omega, const double *kij, int32_t props_per_mixture,
+                     const double *lnk0, const int8_t *hint,
                      const orc_opts *o, int8_t *label, double *beta, double *x,
                      double *y, double *min_tpd, double *tm, int32_t *info, int64_t begin,
                      int64_t end)
@@ -1020,7 +1041,8 @@ void orc_flash_batch(int64_t n, int32_t nc, const double *z, const double *T,
         const double *pc = props_per_mixture ? Pc + m * nc : Pc;
         const double *om = props_per_mixture ? omega + m * nc : omega;
         const double *kk = props_per_mixture ? kij + m * nc * nc : kij;
-        orc_flash_one(nc, z + m * nc, T[m], P[m], tc, pc, om, kk, o, &r);
+        orc_flash_one(nc, z + m * nc, T[m], P[m], tc, pc, om, kk, lnk0 ? lnk0 + m * nc : NULL,
+                      hint ? (int)hint[m] : -1, o, &r);
         label[m] = (int8_t)r.label;
         beta[m] = r.beta;
         for (int i = 0; i < nc; ++i) { x[m * nc + i] = r.x[i]; y[m * nc + i] = r.y[i]; }

@@ -5,7 +5,7 @@ The compute path is the HIP library built from ``csrc/`` (C ABI in
 """
 from . import _capi  # noqa: F401
 from .api import (FlashResult, eval_phase, flash, flash_autograd, flash_backward,  # noqa: F401
-                  flash_ragged, stability)
+                  flash_ragged, hint_from_probability, stability)
 
-__all__ = ["flash", "flash_ragged", "stability", "flash_backward", "flash_autograd",
+__all__ = ["flash", "flash_ragged", "stability", "hint_from_probability", "flash_backward", "flash_autograd",
            "eval_phase", "FlashResult"]

@@ -39,13 +39,43 @@ def _stream_handle(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
-def make_problem(z, T, P, Tc, Pc, omega, kij):
+def make_problem(z, T, P, Tc, Pc, omega, kij, lnk0=None, hint=None):
     n, nc = z.shape
     per = 1 if Tc.dim() == 2 else 0
     p = _capi.Problem(n=n, nc=nc, props_per_mixture=per, z=_ptr(z).value, T=_ptr(T).value,
                       P=_ptr(P).value, Tc=_ptr(Tc).value, Pc=_ptr(Pc).value,
-                      omega=_ptr(omega).value, kij=_ptr(kij).value)
+                      omega=_ptr(omega).value, kij=_ptr(kij).value,
+                      lnk0=None if lnk0 is None else _ptr(lnk0).value,
+                      hint=None if hint is None else _ptr(hint).value)
     return p
+
+
+def hint_from_probability(p, p_l: float, p_r: float) -> torch.Tensor:
+    """The threshold rule of Sec. 4 for a classifier's probability p that a
+    mixture is stable: hint 0 (stable) where p >= p_r, else 1 (unstable)
+    where p <= p_l, else -1 (run the stability analysis); p_l <= p_r.  With
+    p_l = p_r the classifier alone decides."""
+    if not p_l <= p_r:
+        raise ValueError("p_l must not exceed p_r")
+    p = torch.as_tensor(p)
+    h = torch.full(p.shape, -1, dtype=torch.int8, device=p.device)
+    h[p <= p_l] = 1
+    h[p >= p_r] = 0
+    return h
+
+
+def _warm_start(lnk0, hint, n, nc, dev):
+    """The optional per-mixture inputs on the device: lnk0 (n, nc) float64,
+    hint (n,) int8."""
+    if lnk0 is not None:
+        lnk0 = _f64(lnk0, dev)
+        if tuple(lnk0.shape) != (n, nc):
+            raise ValueError(f"lnk0 must have shape ({n}, {nc})")
+    if hint is not None:
+        hint = torch.as_tensor(hint, dtype=torch.int8, device=dev).contiguous()
+        if tuple(hint.shape) != (n,):
+            raise ValueError(f"hint must have shape ({n},)")
+    return lnk0, hint
 
 
 def _workspace(nbytes: int, device) -> torch.Tensor:
@@ -55,18 +85,22 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 
 def flash(z, T, P, Tc, Pc, omega, kij, *, keep_factor: bool = False, stream=None,
-          out: FlashResult | None = None, **opts) -> FlashResult:
+          out: FlashResult | None = None, lnk0=None, hint=None, **opts) -> FlashResult:
     """Isothermal two-phase SRK flash of n mixtures on the current GPU.
 
     z (n, nc), T (n,), P (n,) and the component set Tc, Pc, omega (nc,), kij
-    (nc, nc) are float64 tensors (moved to the GPU if needed).  Keyword
-    options override ptflash_default_options (e.g. form=_capi.FORM_PLAIN)."""
+    (nc, nc) are float64 tensors (moved to the GPU if needed).  Optional
+    lnk0 (n, nc): initial ln K in place of Wilson's; hint (n,)
+    int8: 0 known stable, 1 known unstable, else none (ptflash_problem).
+    Keyword options override ptflash_default_options (e.g.
+    form=_capi.FORM_PLAIN)."""
     dev = torch.device("cuda", torch.cuda.current_device())
     z, T, P = _f64(z, dev), _f64(T, dev), _f64(P, dev)
     Tc, Pc, omega, kij = (_f64(a, dev) for a in (Tc, Pc, omega, kij))
     n, nc = z.shape
+    lnk0, hint = _warm_start(lnk0, hint, n, nc, dev)
     o = _capi.default_options(keep_factor=int(keep_factor), **opts)
-    prob = make_problem(z, T, P, Tc, Pc, omega, kij)
+    prob = make_problem(z, T, P, Tc, Pc, omega, kij, lnk0, hint)
     if out is None:
         out = FlashResult(
             label=torch.empty(n, dtype=torch.int8, device=dev),
@@ -90,19 +124,22 @@ def flash(z, T, P, Tc, Pc, omega, kij, *, keep_factor: bool = False, stream=None
     rc = L.ptflash_flash(C.byref(prob), C.byref(o), C.byref(res), _ptr(ws), ws_bytes,
                          _stream_handle(stream))
     _capi.check(rc, "ptflash_flash")
-    out._keepalive = (z, T, P, Tc, Pc, omega, kij, ws)  # until the stream is done
+    out._keepalive = (z, T, P, Tc, Pc, omega, kij, lnk0, hint, ws)  # until the stream is done
     return out
 
 
-def stability(z, T, P, Tc, Pc, omega, kij, *, stream=None, **opts) -> FlashResult:
+def stability(z, T, P, Tc, Pc, omega, kij, *, stream=None, lnk0=None, hint=None,
+              **opts) -> FlashResult:
     """Stability analysis alone (ptflash_stability): label (1 = unstable), tm
-    (the value that decided it), iters, status and flops; beta, x, y are None."""
+    (the value that decided it), iters, status and flops; beta, x, y are None.
+    lnk0 and hint as in flash."""
     dev = torch.device("cuda", torch.cuda.current_device())
     z, T, P = _f64(z, dev), _f64(T, dev), _f64(P, dev)
     Tc, Pc, omega, kij = (_f64(a, dev) for a in (Tc, Pc, omega, kij))
     n, nc = z.shape
+    lnk0, hint = _warm_start(lnk0, hint, n, nc, dev)
     o = _capi.default_options(**opts)
-    prob = make_problem(z, T, P, Tc, Pc, omega, kij)
+    prob = make_problem(z, T, P, Tc, Pc, omega, kij, lnk0, hint)
     out = FlashResult(label=torch.empty(n, dtype=torch.int8, device=dev), beta=None, x=None,
                       y=None, iters=torch.empty((n, _capi.NITERS), dtype=torch.int16, device=dev),
                       status=torch.empty(n, dtype=torch.int16, device=dev),
@@ -117,7 +154,7 @@ def stability(z, T, P, Tc, Pc, omega, kij, *, stream=None, **opts) -> FlashResul
     rc = L.ptflash_stability(C.byref(prob), C.byref(o), C.byref(res), _ptr(ws), ws_bytes,
                              _stream_handle(stream))
     _capi.check(rc, "ptflash_stability")
-    out._keepalive = (z, T, P, Tc, Pc, omega, kij, ws)
+    out._keepalive = (z, T, P, Tc, Pc, omega, kij, lnk0, hint, ws)
     return out
 
 

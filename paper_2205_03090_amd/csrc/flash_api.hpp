@@ -30,6 +30,8 @@ struct FlashArgs {
     double *factor;
     double *tm;            // nullable: the value that decided stability
     int stability_only;    // stop after the stability decision (no split)
+    const double *lnk0;    // nullable: initial ln K of the split substitutions
+    const int8_t *hint;    // nullable: 0 known stable, 1 known unstable
 };
 
 // Arguments of the backward kernel.

@@ -49,7 +49,8 @@ namespace ptf {
 constexpr uint32_t kStInvalid = 0x0001u, kStShortcut = 0x0002u, kStSaRan = 0x0004u,
                    kStSaUnconv = 0x0008u, kStSplitTr = 0x0010u, kStSplitUnconv = 0x0020u,
                    kStSplitTrivial = 0x0040u, kStSplitFailed = 0x0080u,
-                   kStRrNoRoot = 0x0100u, kStSwapped = 0x0200u, kStStepCap = 0x0400u;
+                   kStRrNoRoot = 0x0100u, kStSwapped = 0x0200u, kStStepCap = 0x0400u,
+                   kStHinted = 0x0800u;
 
 // A split whose smaller phase holds less than this fraction of the feed is
 // reported as failed (single phase).
@@ -65,7 +66,7 @@ struct MixRec {
     double s[NC], b[NC];   // EOS constants at (T, P): sqrt(A_i), B_i
     double lnz[NC];        // ln of the normalised feed
     double d[NC];          // ln z + ln phi(z)
-    double lkw[NC];        // Wilson ln K
+    double lkw[NC];        // initial ln K: Wilson's, or the caller's
     double lk[NC];         // split ln K (PreSs case 3, SaFin), then n^V (SpSs -> SpNt)
     double lw[2][NC];      // ln W of the stability trials (start of SaTr, final)
     double tm[2];          // final tm of the trials
@@ -313,7 +314,8 @@ template <int NC, bool PM>
 struct FeedItem {
     static constexpr int WAVES = 1;   // minimum wavefronts per SIMD
     static constexpr bool kPerMixture = PM;   // one component set per mixture
-    static constexpr uint32_t OUT = (1u << L_SA) | (1u << L_SAFIN) | (1u << L_PRE);   // lists the steps append to
+    static constexpr uint32_t OUT = (1u << L_SA) | (1u << L_SAFIN) | (1u << L_PRE) |
+                                    (1u << L_SPLIT);   // lists the steps append to
     Outbox ob;   // list entries produced by the current step
     static constexpr int LIST = -1;   // input: mixtures 0..n-1
     static constexpr int LIST2 = -1;   // second input list, read after LIST
@@ -344,6 +346,7 @@ struct FeedItem {
             ok = ok && (pp.K[i * NC + i] == 0.0);
 #pragma unroll
             for (int j = 0; j < i; ++j) ok = ok && (pp.K[i * NC + j] == pp.K[j * NC + i]);
+            if (a.lnk0) ok = ok && isfinite(a.lnk0[m * NC + i]);
         }
         if (!ok) {
             // invalid input: report the raw feed as a single phase
@@ -360,13 +363,30 @@ struct FeedItem {
 
     __device__ __forceinline__ bool step(const Ctx<NC> &c)
     {
+        const FlashArgs &a = c.a;
+        const int hint = a.hint ? (int)a.hint[m] : -1;
+        if (hint == 0) {
+            // known stable (the caller's classifier)
+            int16_t it[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            write_outputs_single<NC>(c, m, z, kStHinted, 0, it);
+            if (a.tm) a.tm[m] = NAN;
+            return true;
+        }
         const Props pp = mix_props<NC, PM>(c.pr, m);
         uint32_t fl = 0;
         Phase<NC> o;
         phase_eval<NC>(o, e, pp.K, z, fl);
         MixRec<NC> &r = c.rec[m];
-        double lkw[NC];
-        wilson_lnk<NC, PM>(lkw, pp, T, P);
+        // the initial ln K: the caller's (an initializer's estimate or a
+        // previous result), else Wilson's; it starts both the substitutions
+        // and the two stability trials
+        double ls[NC];
+        if (a.lnk0) {
+#pragma unroll
+            for (int i = 0; i < NC; ++i) ls[i] = a.lnk0[m * NC + i];
+        } else {
+            wilson_lnk<NC, PM>(ls, pp, T, P);
+        }
 #pragma unroll
         for (int i = 0; i < NC; ++i) {
             const double lz = log(z[i]);
@@ -374,17 +394,30 @@ struct FeedItem {
             r.b[i] = e.b[i];
             r.lnz[i] = lz;
             r.d[i] = lz + o.lnphi[i];
-            r.lkw[i] = lkw[i];
+            r.lkw[i] = ls[i];
         }
         fl += 8 * NC;
+        if (hint == 1) {
+            // known unstable: the split starts at once
+            if (a.tm) a.tm[m] = NAN;
+            if (a.stability_only) {
+                int16_t it[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                write_outputs_unstable<NC>(c, m, kStHinted, fl, it);
+                return true;
+            }
+            route_mixture<NC>(r, ob, m, true, kStHinted, fl, 0, ls, 0.5);
+            return true;
+        }
         // the first Rachford-Rice solve of the initial substitutions decides
         // case 1 here; the other mixtures repeat it in PreSs
         double x[NC], y[NC], theta = 0.5;
         uint32_t frr = 0;
-        const bool in = xy_from_lnk<NC>(x, y, lkw, z, theta, frr) && theta > 0.0 && theta < 1.0;
+        const bool in = xy_from_lnk<NC>(x, y, ls, z, theta, frr) && theta > 0.0 && theta < 1.0;
         if (!in) {
-            route_mixture<NC>(r, ob, m, false, kStSaRan, fl + frr, 0, lkw, theta);
+            route_mixture<NC>(r, ob, m, false, kStSaRan, fl + frr, 0, ls, theta);
         } else {
+#pragma unroll
+            for (int i = 0; i < NC; ++i) r.lk[i] = ls[i];
             r.fl = fl;
             ob.put(L_PRE, (uint32_t)m);
         }
@@ -421,7 +454,7 @@ struct PreSsItem {
             e.s[i] = r.s[i];
             e.b[i] = r.b[i];
             d[i] = r.d[i];
-            lk[i] = r.lkw[i];
+            lk[i] = r.lk[i];
         }
         fl = r.fl;
         theta = 0.5;

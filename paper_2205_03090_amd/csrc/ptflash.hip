@@ -97,6 +97,8 @@ static void fill_args(FlashArgs &a, const ptflash_problem *p, const ptflash_opti
     a.factor = r->factor;
     a.tm = r->tm;
     a.stability_only = 0;
+    a.lnk0 = p->lnk0;
+    a.hint = p->hint;
 }
 
 // Compile-time dispatch over the component count.
@@ -605,7 +607,7 @@ int ptflash_flash_ragged(const ptflash_ragged_problem *p, const ptflash_options 
             const int64_t cnt = ((int64_t)hc[nc] - c0) < ch ? ((int64_t)hc[nc] - c0) : ch;
             const uint32_t *cid = ids + st.s[nc] + c0;
             RaggedMove<kMinNc>::run(nc, true, cnt, cid, in, u, p->off, rr, s);
-            ptflash_problem sub{cnt, nc, 1, u.z, u.T, u.P, u.Tc, u.Pc, u.om, u.K};
+            ptflash_problem sub{cnt, nc, 1, u.z, u.T, u.P, u.Tc, u.Pc, u.om, u.K, nullptr, nullptr};
             ptflash_result sr{u.label, u.beta, u.x, u.y, u.iters, u.status, u.flops, nullptr,
                               r->tm ? u.tm : nullptr};
             if (fws_bytes < ptflash_workspace_bytes(&sub, o)) return PTFLASH_EWORKSPACE;

@@ -81,3 +81,14 @@ def test_ragged_entry_rejects_malformed_calls_without_gpu():
     # the workspace does not grow with nc beyond what one chunk needs
     big = _capi.RaggedProblem(**{**full, "n": 1 << 22})
     assert L.ptflash_ragged_workspace_bytes(C.byref(big), C.byref(o)) < 64 * 2 ** 30
+
+
+def test_hint_from_probability():
+    import torch
+    from paper_2205_03090_amd import api
+    p = torch.tensor([0.0, 0.1, 0.3, 0.5, 0.7, 0.9, 1.0], dtype=torch.float64)
+    assert api.hint_from_probability(p, 0.3, 0.7).tolist() == [1, 1, 1, -1, 0, 0, 0]
+    # p_l = p_r: the classifier alone decides, stable from the threshold on
+    assert api.hint_from_probability(p, 0.5, 0.5).tolist() == [1, 1, 1, 0, 0, 0, 0]
+    with pytest.raises(ValueError):
+        api.hint_from_probability(p, 0.6, 0.4)
