@@ -156,11 +156,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--flash-only", action="store_true",
+                    help="time the flash alone: no adjoint, stability-only, warm-start, "
+                         "plain-form or graph legs (for profiler runs)")
     ap.add_argument("--graph", action="store_true",
                     help="also time replays of the persistent flash captured in a HIP graph")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
+    if args.flash_only:
+        args.no_adjoint, args.plain_steps, args.graph = True, 0, False
     if args.calibrate_copy:
         import torch
         a = torch.ones(2 ** 27, dtype=torch.float64, device="cuda")
@@ -264,17 +269,36 @@ def main():
         rec["fwd_adjoint"] = {"value": w.n * args.steps / wall_a, "unit": "flashes/s",
                               "ms_per_step": wall_a * 1e3 / args.steps,
                               "nan_grad_frac": float(torch.isnan(bw[1]).double().mean().item())}
-    # stability analysis alone (no phase split), as used to label samples
-    st_out = api.stability(z, T, P, Tc, Pc, om, kij)
-    torch.cuda.synchronize()
-    ts0 = time.perf_counter()
-    for _ in range(args.steps):
+    if not args.flash_only:
+        # stability analysis alone (no phase split), as used to label samples
         st_out = api.stability(z, T, P, Tc, Pc, om, kij)
-    torch.cuda.synchronize()
-    wall_s = time.perf_counter() - ts0
-    rec["stability_only"] = {"value": w.n * args.steps / wall_s, "unit": "mixtures/s",
-                             "ms_per_step": wall_s * 1e3 / args.steps,
-                             "unstable_frac": float((st_out.label == 1).double().mean().item())}
+        torch.cuda.synchronize()
+        ts0 = time.perf_counter()
+        for _ in range(args.steps):
+            st_out = api.stability(z, T, P, Tc, Pc, om, kij)
+        torch.cuda.synchronize()
+        wall_s = time.perf_counter() - ts0
+        rec["stability_only"] = {"value": w.n * args.steps / wall_s, "unit": "mixtures/s",
+                                 "ms_per_step": wall_s * 1e3 / args.steps,
+                                 "unstable_frac": float((st_out.label == 1).double().mean().item())}
+        # warm start (Sec. 4's integration points) with exact inputs: each mixture
+        # hinted with this flash's own label and started from its converged ln K
+        # (zeros where single phase: unused behind a stable hint), the bound of
+        # the acceleration by a classifier and an initializer
+        two = (out.label == 1) & ((out.status.to(torch.int32) & _capi.ST["SPLIT_UNCONV"]) == 0)
+        lnk0 = torch.where(two[:, None], torch.log(out.y / out.x), torch.zeros_like(out.x))
+        hint = torch.where(two, 1, 0).to(torch.int8)
+        wo = api.flash(z, T, P, Tc, Pc, om, kij, lnk0=lnk0, hint=hint)
+        torch.cuda.synchronize()
+        tw0 = time.perf_counter()
+        for _ in range(args.steps):
+            api.flash(z, T, P, Tc, Pc, om, kij, lnk0=lnk0, hint=hint, out=wo)
+        torch.cuda.synchronize()
+        wall_w = time.perf_counter() - tw0
+        rec["warm_start"] = {"value": w.n * args.steps / wall_w, "unit": "flashes/s",
+                             "ms_per_step": wall_w * 1e3 / args.steps,
+                             "max_beta_change": float((wo.beta - out.beta)[two].abs().max().item())
+                             if bool(two.any()) else 0.0}
     # the same persistent flash captured once into a HIP graph and replayed
     if args.graph:
         g = torch.cuda.CUDAGraph()
