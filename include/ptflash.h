@@ -258,6 +258,9 @@ typedef struct {
     const double *Pc;       /* off[n] */
     const double *omega;    /* off[n] */
     const double *kij;      /* sum of nc_of[m]^2 */
+    const double *lnk0;     /* NULL or off[n]: initial ln K, packed like z
+                               (the meaning of ptflash_problem.lnk0) */
+    const int8_t *hint;     /* NULL or n: the meaning of ptflash_problem.hint */
 } ptflash_ragged_problem;
 
 /* Bytes of device workspace ptflash_flash_ragged needs (depends on n and

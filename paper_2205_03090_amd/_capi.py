@@ -34,7 +34,7 @@ class Problem(C.Structure):
 class RaggedProblem(C.Structure):
     _fields_ = [("n", C.c_int64), ("nc_of", _vp), ("off", _vp), ("koff", _vp), ("z", _vp),
                 ("T", _vp), ("P", _vp), ("Tc", _vp), ("Pc", _vp), ("omega", _vp),
-                ("kij", _vp)]
+                ("kij", _vp), ("lnk0", _vp), ("hint", _vp)]
 
 
 class Options(C.Structure):

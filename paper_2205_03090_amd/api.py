@@ -158,10 +158,12 @@ def stability(z, T, P, Tc, Pc, omega, kij, *, stream=None, lnk0=None, hint=None,
     return out
 
 
-def flash_ragged(z, T, P, nc_of, off, koff, Tc, Pc, omega, kij, *, stream=None, **opts):
+def flash_ragged(z, T, P, nc_of, off, koff, Tc, Pc, omega, kij, *, stream=None, lnk0=None,
+                 hint=None, **opts):
     """Flash of a ragged batch (mixtures with their own nc and component set,
     packed as described for ptflash_ragged_problem): z, Tc, Pc, omega hold
-    off[n] values, kij the nc_of[m]^2 blocks at koff[m].  Returns a
+    off[n] values, kij the nc_of[m]^2 blocks at koff[m]; the optional lnk0
+    (off[n], packed like z) and hint (n,) as in flash.  Returns a
     FlashResult whose x and y are packed like z."""
     dev = torch.device("cuda", torch.cuda.current_device())
     z, T, P, Tc, Pc, omega, kij = (_f64(a, dev) for a in (z, T, P, Tc, Pc, omega, kij))
@@ -170,11 +172,21 @@ def flash_ragged(z, T, P, nc_of, off, koff, Tc, Pc, omega, kij, *, stream=None, 
     koff = torch.as_tensor(koff, dtype=torch.int64, device=dev).contiguous()
     n = T.shape[0]
     tot = z.shape[0]
+    if lnk0 is not None:
+        lnk0 = _f64(lnk0, dev)
+        if tuple(lnk0.shape) != (tot,):
+            raise ValueError(f"lnk0 must have shape ({tot},), packed like z")
+    if hint is not None:
+        hint = torch.as_tensor(hint, dtype=torch.int8, device=dev).contiguous()
+        if tuple(hint.shape) != (n,):
+            raise ValueError(f"hint must have shape ({n},)")
     o = _capi.default_options(**opts)
     prob = _capi.RaggedProblem(n=n, nc_of=_ptr(nc_of).value, off=_ptr(off).value,
                                koff=_ptr(koff).value, z=_ptr(z).value, T=_ptr(T).value,
                                P=_ptr(P).value, Tc=_ptr(Tc).value, Pc=_ptr(Pc).value,
-                               omega=_ptr(omega).value, kij=_ptr(kij).value)
+                               omega=_ptr(omega).value, kij=_ptr(kij).value,
+                               lnk0=None if lnk0 is None else _ptr(lnk0).value,
+                               hint=None if hint is None else _ptr(hint).value)
     out = FlashResult(
         label=torch.empty(n, dtype=torch.int8, device=dev),
         beta=torch.empty(n, dtype=torch.float64, device=dev),
@@ -194,7 +206,7 @@ def flash_ragged(z, T, P, nc_of, off, koff, Tc, Pc, omega, kij, *, stream=None, 
     rc = L.ptflash_flash_ragged(C.byref(prob), C.byref(o), C.byref(res), _ptr(ws), ws_bytes,
                                 _stream_handle(stream))
     _capi.check(rc, "ptflash_flash_ragged")
-    out._keepalive = (z, T, P, nc_of, off, koff, Tc, Pc, omega, kij, ws)
+    out._keepalive = (z, T, P, nc_of, off, koff, Tc, Pc, omega, kij, lnk0, hint, ws)
     return out
 
 

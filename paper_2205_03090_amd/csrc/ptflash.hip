@@ -209,10 +209,13 @@ ragged_sort(int64_t n, const int32_t *__restrict__ nc_of, const int64_t *__restr
 struct RaggedIn {
     const int64_t *off, *koff;
     const double *z, *T, *P, *Tc, *Pc, *om, *K;
+    const double *lnk0;   // optional warm-start inputs (null: none)
+    const int8_t *hint;
 };
 
 struct Uniform {   // one gathered uniform-nc chunk
-    double *z, *T, *P, *Tc, *Pc, *om, *K;
+    double *z, *T, *P, *Tc, *Pc, *om, *K, *lnk0;
+    int8_t *hint;
     int8_t *label;
     double *beta, *x, *y, *tm;
     int16_t *iters;
@@ -222,7 +225,8 @@ struct Uniform {   // one gathered uniform-nc chunk
 
 // Gather of one uniform chunk, one thread per value (coalesced stores, and
 // loads that walk each mixture's contiguous rows): the per-component rows
-// (z, Tc, Pc, omega; T and P with component 0) ...
+// (z, Tc, Pc, omega and the optional initial ln K; T, P and the optional
+// hint with component 0) ...
 template <int NC>
 __global__ void __launch_bounds__(kBlock)
 ragged_gather_rows(int64_t cnt, const uint32_t *__restrict__ ids, RaggedIn in, Uniform u)
@@ -237,9 +241,11 @@ ragged_gather_rows(int64_t cnt, const uint32_t *__restrict__ ids, RaggedIn in, U
     u.Tc[t] = in.Tc[o];
     u.Pc[t] = in.Pc[o];
     u.om[t] = in.om[o];
+    if (in.lnk0) u.lnk0[t] = in.lnk0[o];
     if (e == 0) {
         u.T[j] = in.T[m];
         u.P[j] = in.P[m];
+        if (in.hint) u.hint[j] = in.hint[m];
     }
 }
 
@@ -351,7 +357,7 @@ static size_t ragged_ws_layout(int64_t n, int form, size_t *flash_off)
     b += align256((size_t)n * 4);
     b += align256(ch * C * 8) * 6 + align256(ch * C * C * 8) + align256(ch * 8) * 3 +
          align256(ch) + align256(ch * PTFLASH_NITERS * 2) + align256(ch * 2) + align256(ch * 4) +
-         align256(ch * 8);
+         align256(ch * 8) + align256(ch * C * 8) + align256(ch);
     *flash_off = b;
     size_t fw = 0;
     if (Dispatch<WsF>::run(kMaxNc, (int64_t)ch, form, &fw) != PTFLASH_OK) return 0;
@@ -577,6 +583,8 @@ int ptflash_flash_ragged(const ptflash_ragged_problem *p, const ptflash_options 
     u.status = (uint16_t *)takeb(ch * 2);
     u.flops = (uint32_t *)takeb(ch * 4);
     u.tm = (double *)takeb(ch * 8);
+    u.lnk0 = (double *)takeb(ch * C * 8);
+    u.hint = (int8_t *)takeb(ch);
     void *fws = (char *)ws + foff;
     const size_t fws_bytes = ws_bytes - foff;
 
@@ -601,13 +609,15 @@ int ptflash_flash_ragged(const ptflash_ragged_problem *p, const ptflash_options 
         hipLaunchKernelGGL(ragged_invalid, dim3((unsigned)((hc[0] + kBlock - 1) / kBlock)),
                            dim3(kBlock), 0, s, (int64_t)hc[0], ids, p->off, p->z, rr);
     if (hipGetLastError() != hipSuccess) return PTFLASH_EHIP;
-    const RaggedIn in{p->off, p->koff, p->z, p->T, p->P, p->Tc, p->Pc, p->omega, p->kij};
+    const RaggedIn in{p->off, p->koff, p->z, p->T, p->P, p->Tc, p->Pc, p->omega, p->kij,
+                      p->lnk0, p->hint};
     for (int nc = kMinNc; nc <= kMaxNc; ++nc) {
         for (int64_t c0 = 0; c0 < (int64_t)hc[nc]; c0 += ch) {
             const int64_t cnt = ((int64_t)hc[nc] - c0) < ch ? ((int64_t)hc[nc] - c0) : ch;
             const uint32_t *cid = ids + st.s[nc] + c0;
             RaggedMove<kMinNc>::run(nc, true, cnt, cid, in, u, p->off, rr, s);
-            ptflash_problem sub{cnt, nc, 1, u.z, u.T, u.P, u.Tc, u.Pc, u.om, u.K, nullptr, nullptr};
+            ptflash_problem sub{cnt, nc, 1, u.z, u.T, u.P, u.Tc, u.Pc, u.om, u.K,
+                                p->lnk0 ? u.lnk0 : nullptr, p->hint ? u.hint : nullptr};
             ptflash_result sr{u.label, u.beta, u.x, u.y, u.iters, u.status, u.flops, nullptr,
                               r->tm ? u.tm : nullptr};
             if (fws_bytes < ptflash_workspace_bytes(&sub, o)) return PTFLASH_EWORKSPACE;

@@ -5,7 +5,8 @@ against the CPU oracle given the same inputs.
 Cases: nc 8 (3,000 mixtures) and nc 12 (2,000, the lane-group stages) with a
 perturbed initial ln K on every row and a hint mix of right, wrong and absent
 labels, in both forms of the pipeline; a warm start from a previous GPU
-result; the stability-only entry with hints; invalid initial K.
+result; the stability-only entry with hints; invalid initial K; the ragged
+entry (3,500 mixtures, nc 2-20) with the same inputs.
 """
 import numpy as np
 import pytest
@@ -129,3 +130,39 @@ def test_non_finite_initial_k_is_invalid():
         _flash(w, lnk0=lnk0[:, :4])
     with pytest.raises(ValueError):
         _flash(w, hint=np.zeros(w.n - 1, np.int8))
+
+
+def test_ragged_warm_start():
+    # the ragged entry gathers the initial ln K (packed like z) and the hints
+    # with the rest of each uniform group: every group equals, bit for bit,
+    # the uniform flash given the same inputs, and matches the oracle
+    w = workloads.ragged_workload("ragged_ws", 35, 3500)
+    rng = np.random.Generator(np.random.PCG64(36))
+    lnk0 = np.zeros(w.off[-1])
+    for m in range(w.n):
+        a, b = w.off[m], w.off[m + 1]
+        lk = oracle.wilson_lnk(w.Tc[a:b], w.Pc[a:b], w.omega[a:b], w.T[m], w.P[m])
+        lnk0[a:b] = lk * (1.0 + 0.1 * rng.standard_normal(b - a))
+    hint = rng.choice(np.array([-1, -1, 0, 1], dtype=np.int8), w.n)
+    print(f"case ragged warm start n={w.n}", flush=True)
+    r = api.flash_ragged(w.z, w.T, w.P, w.nc_of, w.off, w.koff, w.Tc, w.Pc, w.omega, w.kij,
+                         lnk0=lnk0, hint=hint)
+    torch.cuda.synchronize()
+    g = gpu_to_numpy(r)
+    for nc in (2, 4, 6, 8, 12, 16, 20):
+        idx, gw = w.group(nc)
+        rows = w.off[idx][:, None] + np.arange(nc)[None, :]
+        gg = dict(label=g["label"][idx], beta=g["beta"][idx], x=g["x"][rows], y=g["y"][rows],
+                  iters=g["iters"][idx], status=g["status"][idx], tm=g["tm"][idx])
+        u = _flash(gw, lnk0=lnk0[rows], hint=hint[idx])
+        for k in ("label", "beta", "x", "y", "iters", "status", "tm"):
+            assert np.array_equal(gg[k], u[k], equal_nan=True), (nc, k)
+        if nc in (4, 12):
+            o = oracle.flash(gw, threads=8, want_min_tpd=1, lnk0=lnk0[rows], hint=hint[idx])
+            rep = compare(gg, o, w=gw)
+            print(f"[ragged warm start nc={nc}] {rep}", flush=True)
+            assert rep["label_mismatch"] == 0 and rep["value_mismatch"] == 0
+            assert rep["single_mismatch"] == 0
+    with pytest.raises(ValueError):
+        api.flash_ragged(w.z, w.T, w.P, w.nc_of, w.off, w.koff, w.Tc, w.Pc, w.omega, w.kij,
+                         lnk0=lnk0[:-1])
