@@ -166,3 +166,21 @@ def test_ragged_warm_start():
     with pytest.raises(ValueError):
         api.flash_ragged(w.z, w.T, w.P, w.nc_of, w.off, w.koff, w.Tc, w.Pc, w.omega, w.kij,
                          lnk0=lnk0[:-1])
+
+
+def test_stability_only_with_initial_k():
+    # the trials start from the caller's K: the decisions match the oracle's
+    # given the same K, and the stability entry equals the full flash's
+    # decision bit for bit
+    w = workloads.uniform_workload("wss", 6200, 3000, 8, 0.5, (200.0, 600.0), (1e5, 2e7))
+    lnk0, _ = _inputs(w, 29)
+    print(f"case stability with initial K n={w.n}", flush=True)
+    r = api.stability(w.z, w.T, w.P, w.Tc, w.Pc, w.omega, w.kij, lnk0=lnk0)
+    torch.cuda.synchronize()
+    lab = r.label.cpu().numpy()
+    o = oracle.flash(w, threads=8, want_min_tpd=1, lnk0=lnk0)
+    unst = o["info"][:, oracle.INFO_FIELDS.index("unstable")] == 1
+    band = np.abs(o["min_tpd"]) > 1e-9
+    assert not np.any(band & ((lab == 1) != unst))
+    f = _flash(w, lnk0=lnk0)
+    assert np.array_equal(r.tm.cpu().numpy(), f["tm"], equal_nan=True)
