@@ -184,3 +184,14 @@ def test_stability_only_with_initial_k():
     assert not np.any(band & ((lab == 1) != unst))
     f = _flash(w, lnk0=lnk0)
     assert np.array_equal(r.tm.cpu().numpy(), f["tm"], equal_nan=True)
+
+
+def test_warm_start_forms_agree():
+    # the plain form takes the same decisions on the same inputs: bit for bit
+    w = workloads.uniform_workload("wsf", 6300, 3000, 10, 0.5, (200.0, 600.0), (1e5, 2e7))
+    lnk0, hint = _inputs(w, 31)
+    print(f"case warm start forms nc={w.nc} n={w.n}", flush=True)
+    a = _flash(w, lnk0=lnk0, hint=hint, lanes_per_mixture=1, form=_capi.FORM_PERSISTENT)
+    b = _flash(w, lnk0=lnk0, hint=hint, lanes_per_mixture=1, form=_capi.FORM_PLAIN)
+    for k in ("label", "beta", "x", "y", "iters", "status", "flops", "tm"):
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
