@@ -195,3 +195,27 @@ def test_warm_start_forms_agree():
     b = _flash(w, lnk0=lnk0, hint=hint, lanes_per_mixture=1, form=_capi.FORM_PLAIN)
     for k in ("label", "beta", "x", "y", "iters", "status", "flops", "tm"):
         assert np.array_equal(a[k], b[k], equal_nan=True), k
+
+
+def test_resubmission_of_unconverged_splits():
+    # splits stopped by a tight trust-region cap report SPLIT_UNCONV with
+    # their last iterate; submitted again from that iterate's K with the
+    # unstable hint and the default caps, they reach the equilibrium of an
+    # uninterrupted flash
+    w = workloads.nc8_workload(n=20_000)
+    print(f"case re-submission n={w.n}", flush=True)
+    full = _flash(w)
+    cut = _flash(w, max_tr_split=1)
+    st = cut["status"].astype(np.int64)
+    idx = np.where((cut["label"] == 1) & ((st & ST["SPLIT_UNCONV"]) != 0))[0]
+    assert len(idx) > 50
+    again = _flash(w.subset(idx), lnk0=np.log(cut["y"][idx] / cut["x"][idx]),
+                   hint=np.ones(len(idx), np.int8))
+    fs = full["status"][idx].astype(np.int64)
+    ok = (full["label"][idx] == 1) & ((fs & ST["SPLIT_UNCONV"]) == 0)
+    assert np.all(again["label"][ok] == 1)
+    err = np.maximum(np.abs(again["beta"][ok] - full["beta"][idx][ok]),
+                     np.maximum(np.abs(again["x"][ok] - full["x"][idx][ok]).max(1),
+                                np.abs(again["y"][ok] - full["y"][idx][ok]).max(1)))
+    print(f"[re-submission] {len(idx)} unconverged; max err {err.max():.2e}", flush=True)
+    assert np.mean(err < 1e-10) > 0.99 and err.max() < 1e-8
