@@ -24,7 +24,7 @@ class OrcOpts(C.Structure):
                 ("want_min_tpd", C.c_int32), ("max_newton_split", C.c_int32),
                 ("tol_sa_ss", C.c_double), ("tol_sa_tr", C.c_double),
                 ("tol_split_ss", C.c_double), ("tol_split", C.c_double),
-                ("eps_tm", C.c_double)]
+                ("eps_tm", C.c_double), ("decision_only", C.c_int32)]
 
 
 INFO_FIELDS = ["case", "pre", "ss_v", "nt_v", "ss_l", "nt_l", "ss_split",

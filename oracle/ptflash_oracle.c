@@ -92,6 +92,8 @@ typedef struct {
     double tol_split_ss;     /* max |K_new/K - 1| (1e-8)                   */
     double tol_split;        /* refinement target on the residual (1e-13)  */
     double eps_tm;           /* negative-tm threshold (1e-10)              */
+    int32_t decision_only;   /* stop after the stability decision: label =
+                                unstable, no phase split (0)               */
 } orc_opts;
 
 /* oracle-side outcome flags (independent of the library's status bits) */
@@ -938,6 +940,13 @@ int orc_flash_one(int nc, const double *z_in, double T, double P,
     }
 
     res->info[ORC_I_UNSTABLE] = unstable;
+    if (o->decision_only) {
+        /* the stability decision alone (Sec. 2.2.1 and 2.2.3): label 1 for a
+         * mixture the flash would send to the phase split */
+        res->label = unstable;
+        res->info[ORC_I_FLAGS] = (int32_t)flags;
+        return 0;
+    }
     if (!unstable) {
         res->info[ORC_I_FLAGS] = (int32_t)flags;
         return 0;
@@ -1017,6 +1026,7 @@ void orc_default_opts(orc_opts *o)
     o->tol_split_ss = 1e-8;
     o->tol_split = 1e-13;
     o->eps_tm = 1e-10;
+    o->decision_only = 0;
 }
 
 int orc_ninfo(void) { return ORC_NINFO; }

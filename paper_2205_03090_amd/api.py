@@ -39,8 +39,28 @@ def _stream_handle(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
+def _check_shapes(n, nc, T, P, Tc, Pc, omega, kij):
+    """Host-side shape checks before any launch: T, P (n,); a shared
+    component set Tc, Pc, omega (nc,) with kij (nc, nc), or one set per
+    mixture: (n, nc) with kij (n, nc, nc)."""
+    for name, t in (("T", T), ("P", P)):
+        if tuple(t.shape) != (n,):
+            raise ValueError(f"{name} must have shape ({n},), got {tuple(t.shape)}")
+    per = Tc.dim() == 2
+    want = (n, nc) if per else (nc,)
+    for name, t in (("Tc", Tc), ("Pc", Pc), ("omega", omega)):
+        if tuple(t.shape) != want:
+            raise ValueError(f"{name} must have shape {want}, got {tuple(t.shape)}")
+    wk = (n, nc, nc) if per else (nc, nc)
+    if tuple(kij.shape) != wk:
+        raise ValueError(f"kij must have shape {wk}, got {tuple(kij.shape)}")
+
+
 def make_problem(z, T, P, Tc, Pc, omega, kij, lnk0=None, hint=None):
+    if z.dim() != 2:
+        raise ValueError(f"z must have shape (n, nc), got {tuple(z.shape)}")
     n, nc = z.shape
+    _check_shapes(n, nc, T, P, Tc, Pc, omega, kij)
     per = 1 if Tc.dim() == 2 else 0
     p = _capi.Problem(n=n, nc=nc, props_per_mixture=per, z=_ptr(z).value, T=_ptr(T).value,
                       P=_ptr(P).value, Tc=_ptr(Tc).value, Pc=_ptr(Pc).value,
@@ -172,6 +192,7 @@ def flash_ragged(z, T, P, nc_of, off, koff, Tc, Pc, omega, kij, *, stream=None, 
     koff = torch.as_tensor(koff, dtype=torch.int64, device=dev).contiguous()
     n = T.shape[0]
     tot = z.shape[0]
+    _check_ragged(n, tot, P, nc_of, off, koff, Tc, Pc, omega, kij)
     if lnk0 is not None:
         lnk0 = _f64(lnk0, dev)
         if tuple(lnk0.shape) != (tot,):
@@ -210,13 +231,43 @@ def flash_ragged(z, T, P, nc_of, off, koff, Tc, Pc, omega, kij, *, stream=None, 
     return out
 
 
+def _check_ragged(n, tot, P, nc_of, off, koff, Tc, Pc, omega, kij):
+    """Host-side checks of a ragged batch before any launch: sizes of the
+    per-mixture and packed arrays, off[0] = 0, off non-decreasing with
+    off[n] = len(z), and every k block inside kij.  (Rows whose off step
+    differs from nc_of are not an error here: the library reports them
+    INVALID.)"""
+    if tuple(P.shape) != (n,) or tuple(nc_of.shape) != (n,) or tuple(koff.shape) != (n,):
+        raise ValueError("T, P, nc_of and koff must all have shape (n,)")
+    if tuple(off.shape) != (n + 1,):
+        raise ValueError(f"off must have shape ({n + 1},)")
+    for name, t in (("Tc", Tc), ("Pc", Pc), ("omega", omega)):
+        if tuple(t.shape) != (tot,):
+            raise ValueError(f"{name} must be packed like z: shape ({tot},)")
+    if n == 0:
+        return
+    o = off.cpu()
+    if int(o[0]) != 0 or int(o[-1]) != tot or bool((o[1:] < o[:-1]).any()):
+        raise ValueError("off must start at 0, never decrease and end at len(z)")
+    k = koff.cpu()
+    nco = nc_of.cpu().to(torch.int64)
+    if bool((k < 0).any()) or bool((nco < 0).any()) or \
+            int((k + nco * nco).max()) > kij.shape[0]:
+        raise ValueError("every k block koff[m] + nc_of[m]^2 must lie inside kij")
+
+
 def eval_phase(c, T, P, Tc, Pc, omega, kij, *, derivs: bool = True, stream=None):
     """ln phi (n, nc), Z (n,) and Phi = n d ln phi/d n (n, nc, nc) of the SRK
     phase model at compositions c (n, nc)."""
     dev = torch.device("cuda", torch.cuda.current_device())
     c, T, P = _f64(c, dev), _f64(T, dev), _f64(P, dev)
     Tc, Pc, omega, kij = (_f64(a, dev) for a in (Tc, Pc, omega, kij))
+    if c.dim() != 2:
+        raise ValueError(f"c must have shape (n, nc), got {tuple(c.shape)}")
     n, nc = c.shape
+    if Tc.dim() != 1:
+        raise ValueError("eval_phase takes one shared component set")
+    _check_shapes(n, nc, T, P, Tc, Pc, omega, kij)
     lnphi = torch.empty((n, nc), dtype=torch.float64, device=dev)
     Z = torch.empty(n, dtype=torch.float64, device=dev)
     phi = torch.empty((n, nc, nc), dtype=torch.float64, device=dev) if derivs else None
@@ -240,6 +291,11 @@ def flash_backward(z, T, P, Tc, Pc, omega, kij, fwd: FlashResult, g_beta, g_x, g
         raise ValueError("the forward result holds no factor (run flash with keep_factor=True)")
     n, nc = z.shape
     prob = make_problem(z, T, P, Tc, Pc, omega, kij)
+    if tuple(g_beta.shape) != (n,) or tuple(g_x.shape) != (n, nc) or \
+            tuple(g_y.shape) != (n, nc):
+        raise ValueError(f"cotangents must have shapes ({n},), ({n}, {nc}), ({n}, {nc})")
+    if tuple(fwd.x.shape) != (n, nc) or tuple(fwd.factor.shape) != (n, nc * (nc + 1) // 2):
+        raise ValueError("the forward result does not match this problem's shape")
     o = _capi.default_options()
     res = _capi.Result(label=_ptr(fwd.label).value, beta=_ptr(fwd.beta).value,
                        x=_ptr(fwd.x).value, y=_ptr(fwd.y).value, iters=_ptr(fwd.iters).value,

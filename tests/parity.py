@@ -159,3 +159,30 @@ def invariants(w, g) -> dict:
     return dict(two_phase_frac=float(two.mean()), mass_balance=float(mb), sum_x=float(sx),
                 sum_y=float(sy), beta_in_range=brange, single_ok=single_ok,
                 labels_valid=bool(np.all((lab == 0) | (lab == 1))))
+
+
+def assert_parity(rep: dict, o: dict | None = None, path_agree: float = 0.97,
+                  min_two_phase_frac: float = 0.05, alt_frac: float = 0.01,
+                  unconv_frac: float = 0.005) -> None:
+    """The parity bar plus guards that keep it from passing vacuously: no
+    label, value or single-phase mismatch; at most 1 % of the rows inside
+    the min-TPD band (at least one row allowed below 100 rows); at most
+    unconv_frac of the rows without a converged oracle split and alt_frac of
+    the compared two-phase rows on a second valid split; and a floor on the
+    two-phase rows whose values were compared: at least 90 % of the oracle's
+    two-phase rows, which in turn are at least min_two_phase_frac of the
+    rows."""
+    n = rep["n"]
+    assert rep["label_mismatch"] == 0, rep
+    assert rep["value_mismatch"] == 0, rep
+    assert rep["single_mismatch"] == 0, rep
+    assert rep["ss_path_agree"] >= path_agree, rep
+    assert rep["band_excluded"] <= max(0.01 * n, 1 if n < 100 else 0), rep
+    assert rep["ref_unconverged"] <= unconv_frac * n, rep
+    assert rep["alt_split"] <= alt_frac * max(1, rep["two_phase"]), rep
+    if o is not None:
+        o2 = int((np.asarray(o["label"]) == 1).sum())
+        assert o2 >= min_two_phase_frac * n, (o2, rep)
+        assert rep["two_phase"] >= 0.9 * o2, (o2, rep)
+    else:
+        assert rep["two_phase"] >= min_two_phase_frac * n, rep

@@ -92,3 +92,38 @@ def test_hint_from_probability():
     assert api.hint_from_probability(p, 0.5, 0.5).tolist() == [1, 1, 1, 0, 0, 0, 0]
     with pytest.raises(ValueError):
         api.hint_from_probability(p, 0.6, 0.4)
+
+
+def test_binding_checks_shapes_before_any_launch():
+    import numpy as np
+    import torch
+    from paper_2205_03090_amd import api, workloads
+    w = workloads.nc8_workload(n=6, seed=3)
+    t = lambda a: torch.as_tensor(a, dtype=torch.float64)
+    z, T, P, Tc, Pc, om, k = map(t, (w.z, w.T, w.P, w.Tc, w.Pc, w.omega, w.kij))
+    api.make_problem(z, T, P, Tc, Pc, om, k)   # well formed
+    bad = [(z, T[:5], P, Tc, Pc, om, k), (z, T, P[:, None], Tc, Pc, om, k),
+           (z, T, P, Tc[:7], Pc, om, k), (z, T, P, Tc, Pc, om, k[:7]),
+           (z, T, P, Tc[None].repeat(6, 1), Pc, om, k), (z[0], T, P, Tc, Pc, om, k)]
+    for args in bad:
+        with pytest.raises(ValueError):
+            api.make_problem(*args)
+    # per-mixture sets need (n, nc) properties and (n, nc, nc) k
+    rep = lambda a: a[None].repeat(6, *([1] * a.dim()))
+    api.make_problem(z, T, P, rep(Tc), rep(Pc), rep(om), rep(k))
+    with pytest.raises(ValueError):
+        api.make_problem(z, T, P, rep(Tc), rep(Pc), rep(om), k)
+    # ragged offsets
+    nc_of = torch.tensor([2, 3], dtype=torch.int32)
+    off = torch.tensor([0, 2, 5], dtype=torch.int64)
+    koff = torch.tensor([0, 4], dtype=torch.int64)
+    zz, kk = torch.ones(5, dtype=torch.float64), torch.zeros(13, dtype=torch.float64)
+    T2 = torch.ones(2, dtype=torch.float64)
+    api._check_ragged(2, 5, T2, nc_of, off, koff, zz, zz, zz, kk)
+    for o2, k2, kij2 in [(torch.tensor([1, 2, 5]), koff, kk), (torch.tensor([0, 3, 2]), koff, kk),
+                         (torch.tensor([0, 2, 6]), koff, kk), (off, torch.tensor([0, 5]), kk),
+                         (off, koff, kk[:12])]:
+        with pytest.raises(ValueError):
+            api._check_ragged(2, 5, T2, nc_of, o2.to(torch.int64), k2.to(torch.int64), zz, zz,
+                              zz, kij2)
+    assert np.isfinite(w.z).all()

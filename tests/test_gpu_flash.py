@@ -13,7 +13,7 @@ torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
 from paper_2205_03090_amd import _capi, api, workloads  # noqa: E402
-from parity import compare, gpu_to_numpy, invariants  # noqa: E402
+from parity import assert_parity, compare, gpu_to_numpy, invariants  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -33,13 +33,6 @@ def _report(tag, rep):
     print(f"[{tag}] {rep}", flush=True)
 
 
-def _assert_parity(rep, path_agree=0.99):
-    assert rep["label_mismatch"] == 0
-    assert rep["value_mismatch"] == 0
-    assert rep["single_mismatch"] == 0
-    assert rep["ss_path_agree"] >= path_agree
-
-
 def test_nc3_full_parity():
     w = workloads.nc3_workload()
     print(f"case nc3 n={w.n}", flush=True)
@@ -51,7 +44,7 @@ def test_nc3_full_parity():
     _report("nc3 invariants", inv)
     assert inv["mass_balance"] < 1e-13 and inv["sum_x"] < 1e-13 and inv["sum_y"] < 1e-13
     assert inv["single_ok"] and inv["beta_in_range"] and inv["labels_valid"]
-    _assert_parity(rep)
+    assert_parity(rep, o, path_agree=0.99, min_two_phase_frac=0.2)
 
 
 def test_nc8_full_size_sampled_parity():
@@ -67,7 +60,7 @@ def test_nc8_full_size_sampled_parity():
     o = _oracle(w, idx)
     rep = compare(g, o, idx, w=w)
     _report("nc8 sample", rep)
-    _assert_parity(rep)
+    assert_parity(rep, o, path_agree=0.99, min_two_phase_frac=0.15)
 
 
 def test_eval_phase_matches_oracle_and_fd():
@@ -109,12 +102,13 @@ def test_eval_phase_matches_oracle_and_fd():
 
 @pytest.mark.parametrize("n", [1, 63, 65, 1000])
 def test_ragged_sizes(n):
-    w = workloads.nc8_workload(n=n, seed=99)
+    w = workloads.nc8_workload(n=n)
     print(f"case ragged n={n}", flush=True)
     g = _run(w)
-    rep = compare(g, _oracle(w), w=w)
+    o = _oracle(w)
+    rep = compare(g, o, w=w)
     _report(f"ragged {n}", rep)
-    _assert_parity(rep, path_agree=0.95)
+    assert_parity(rep, o, path_agree=0.95, min_two_phase_frac=0.1 if n >= 65 else 0.0)
 
 
 def test_empty_batch():
@@ -124,15 +118,22 @@ def test_empty_batch():
     assert r.label.numel() == 0
 
 
+# seed of each component set; the binary's is the first of 1002 + 100 k whose
+# set (a light and a heavy component) gives two-phase feeds in this T, P box
+# (14.5 % of them; the set of seed 1002 gives none)
+EXTREME_SEED = {2: 1102, 12: 1012, 16: 1016, 20: 1020}
+
+
 @pytest.mark.parametrize("nc", [2, 12, 16, 20])
 def test_extreme_component_counts(nc):
-    w = workloads.uniform_workload(f"nc{nc}", 1000 + nc, 3000, nc, 0.7, (200.0, 600.0),
+    w = workloads.uniform_workload(f"nc{nc}", EXTREME_SEED[nc], 3000, nc, 0.7, (200.0, 600.0),
                                    (1e5, 2e7))
     print(f"case nc={nc}", flush=True)
     g = _run(w)
-    rep = compare(g, _oracle(w), w=w)
+    o = _oracle(w)
+    rep = compare(g, o, w=w)
     _report(f"nc{nc}", rep)
-    _assert_parity(rep, path_agree=0.97)
+    assert_parity(rep, o, path_agree=0.97, min_two_phase_frac=0.08)
 
 
 @pytest.mark.parametrize("nc", [4, 8, 20])
@@ -145,9 +146,10 @@ def test_per_mixture_component_sets(nc):
     inv = invariants(w, g)
     _report(f"pm{nc} invariants", inv)
     assert inv["mass_balance"] < 1e-13 and inv["single_ok"] and inv["labels_valid"]
-    rep = compare(g, _oracle(w), w=w)
+    o = _oracle(w)
+    rep = compare(g, o, w=w)
     _report(f"pm{nc}", rep)
-    _assert_parity(rep, path_agree=0.97)
+    assert_parity(rep, o, path_agree=0.97, min_two_phase_frac=0.1)
     g1 = _run(w, lanes_per_mixture=1)
     gp = _run(w, form=_capi.FORM_PLAIN)
     for k in ("label", "beta", "x", "y", "iters", "status"):

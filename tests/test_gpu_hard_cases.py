@@ -10,7 +10,7 @@ torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
 from paper_2205_03090_amd import _capi, api, workloads  # noqa: E402
-from parity import compare, gpu_to_numpy, invariants  # noqa: E402
+from parity import assert_parity, compare, gpu_to_numpy, invariants  # noqa: E402
 import hard_cases  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -22,7 +22,7 @@ def boundary():
     return hard_cases.boundary_workload(5, 300)
 
 
-def _check_forward(w, tag):
+def _check_forward(w, tag, min_two_phase_frac, unconv_frac):
     r = api.flash(w.z, w.T, w.P, w.Tc, w.Pc, w.omega, w.kij)
     torch.cuda.synchronize()
     g = gpu_to_numpy(r)
@@ -32,15 +32,16 @@ def _check_forward(w, tag):
     o = oracle.flash(w, threads=8, want_min_tpd=1)
     rep = compare(g, o, w=w)
     print(f"[{tag}] {rep}", flush=True)
-    assert rep["label_mismatch"] == 0 and rep["value_mismatch"] == 0
-    assert rep["single_mismatch"] == 0 and rep["ss_path_agree"] >= 0.95
-    assert rep["alt_split"] <= 0.01 * max(1, rep["two_phase"])
+    # near the boundary the oracle's split stops unconverged on a few per
+    # cent of the mixtures (checked there by equal fugacity instead)
+    assert_parity(rep, o, path_agree=0.95, min_two_phase_frac=min_two_phase_frac,
+                  unconv_frac=unconv_frac)
     return g
 
 
 def test_boundary_nc20_forward_parity(boundary):
     print(f"case boundary nc=20 n={boundary.n}", flush=True)
-    g = _check_forward(boundary, "boundary nc20")
+    g = _check_forward(boundary, "boundary nc20", 0.3, 0.03)
     assert 0.2 < (g["label"] == 1).mean() < 0.8   # both sides of the boundary
 
 
@@ -48,7 +49,7 @@ def test_uniform_nc20_forward_parity():
     w = workloads.uniform_workload("c5_uniform", 2020, 2000, 20, 0.3, (200.0, 600.0),
                                    (1e5, 3e7))
     print(f"case uniform nc=20 n={w.n}", flush=True)
-    _check_forward(w, "uniform nc20")
+    _check_forward(w, "uniform nc20", 0.05, 0.005)
 
 
 def _vjp_vs_oracle(w, idx_limit, seed, per_mixture=False):

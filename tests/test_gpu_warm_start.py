@@ -15,7 +15,7 @@ torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
 from paper_2205_03090_amd import _capi, api, workloads  # noqa: E402
-from parity import compare, gpu_to_numpy, invariants  # noqa: E402
+from parity import assert_parity, compare, gpu_to_numpy, invariants  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -46,10 +46,11 @@ def _inputs(w, seed):
     return lnk0, hint
 
 
-@pytest.mark.parametrize("nc,n,lanes,form", [(8, 3000, 1, _capi.FORM_PERSISTENT),
-                                             (8, 3000, 1, _capi.FORM_PLAIN),
-                                             (12, 2000, 16, _capi.FORM_PERSISTENT)])
-def test_warm_start_parity(nc, n, lanes, form):
+# floor: the two-phase share of each set is about 1.3x the floor
+@pytest.mark.parametrize("nc,n,lanes,form,floor", [(8, 3000, 1, _capi.FORM_PERSISTENT, 0.08),
+                                                   (8, 3000, 1, _capi.FORM_PLAIN, 0.08),
+                                                   (12, 2000, 16, _capi.FORM_PERSISTENT, 0.03)])
+def test_warm_start_parity(nc, n, lanes, form, floor):
     w = workloads.uniform_workload(f"ws{nc}", 6100 + nc, n, nc, 0.5, (200.0, 600.0),
                                    (1e5, 2e7))
     lnk0, hint = _inputs(w, 17 + nc)
@@ -60,8 +61,7 @@ def test_warm_start_parity(nc, n, lanes, form):
     o = oracle.flash(w, threads=8, want_min_tpd=1, lnk0=lnk0, hint=hint)
     rep = compare(g, o, w=w)
     print(f"[warm start nc{nc}] {rep}", flush=True)
-    assert rep["label_mismatch"] == 0 and rep["value_mismatch"] == 0
-    assert rep["single_mismatch"] == 0 and rep["ss_path_agree"] >= 0.97
+    assert_parity(rep, o, path_agree=0.97, min_two_phase_frac=floor)
     st = g["status"].astype(np.int64) & 0xFFFF
     hinted = (hint == 0) | (hint == 1)
     assert np.array_equal((st & ST["HINTED"]) != 0, hinted)
@@ -161,8 +161,7 @@ def test_ragged_warm_start():
             o = oracle.flash(gw, threads=8, want_min_tpd=1, lnk0=lnk0[rows], hint=hint[idx])
             rep = compare(gg, o, w=gw)
             print(f"[ragged warm start nc={nc}] {rep}", flush=True)
-            assert rep["label_mismatch"] == 0 and rep["value_mismatch"] == 0
-            assert rep["single_mismatch"] == 0
+            assert_parity(rep, o, path_agree=0.0, min_two_phase_frac=0.05)
     with pytest.raises(ValueError):
         api.flash_ragged(w.z, w.T, w.P, w.nc_of, w.off, w.koff, w.Tc, w.Pc, w.omega, w.kij,
                          lnk0=lnk0[:-1])

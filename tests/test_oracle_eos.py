@@ -201,3 +201,63 @@ def test_tpd_ideal_gas_is_kl_divergence(orc):
         t = orc.tpd(Tc, Pc, om, k, 400.0, 1e-2, z, w)
         assert abs(t - np.sum(w * np.log(w / z))) < 1e-9
         assert abs(orc.tpd(Tc, Pc, om, k, 300.0, 5e6, z, z)) < 1e-13
+
+
+def test_kij_combining_rule_identical_components(orc):
+    # Two components with the same Tc, Pc and omega differ only through
+    # k_12 = k in the combining rule (Appendix A, eq. mixing_rule:
+    # (a alpha)_ij = (1 - k_ij) sqrt(a_i alpha_i a_j alpha_j)).  Then
+    #   A_mix = A_0 (c1^2 + c2^2 + 2 (1 - k) c1 c2) = A_0 (1 - 2 k c1 c2),
+    #   psi_1 - psi_2 = A_0 k (c1 - c2), and from eq. lnphi
+    #   ln phi_1 - ln phi_2 = -(2 A_0 k / B) ln(1 + B/Z) (c1 - c2),
+    # with A_0 the pure-component value (any composition at k = 0) and B
+    # composition-independent.  A sign error (1 + k), a doubled k or a
+    # transposed index in the combining rule fails one of the two identities.
+    rng = _rng(41)
+    for _ in range(200):
+        tc, pc, om = rng.uniform(190, 620), rng.uniform(2e6, 5e6), rng.uniform(0.01, 0.5)
+        Tc, Pc, omega = np.array([tc, tc]), np.array([pc, pc]), np.array([om, om])
+        k = rng.uniform(0.0, 0.3)
+        kij = np.array([[0.0, k], [k, 0.0]])
+        T, P = rng.uniform(200, 600), rng.uniform(1e5, 2e7)
+        c = rng.dirichlet([1, 1])
+        _, i0 = orc.lnphi(Tc, Pc, omega, np.zeros((2, 2)), T, P, c)
+        lp, info = orc.lnphi(Tc, Pc, omega, kij, T, P, c)
+        A0, A, B, Z = i0["A"], info["A"], info["B"], info["Z"]
+        assert abs(info["B"] - i0["B"]) <= 1e-15 * i0["B"]
+        assert abs(A - A0 * (1.0 - 2.0 * k * c[0] * c[1])) <= 1e-14 * A0
+        ref = -(2.0 * A0 * k / B) * np.log1p(B / Z) * (c[0] - c[1])
+        assert abs((lp[0] - lp[1]) - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
+def test_kij_enters_symmetric_pairs_only(orc):
+    # A ternary with k_12 = k_21 = k and the rest zero: exchanging the
+    # compositions of components 1 and 2 (identical pure properties for 1
+    # and 2) leaves A unchanged and exchanges ln phi_1 and ln phi_2, while
+    # component 3 (not in the pair) keeps its ln phi; with k = 0 the value of
+    # A is the square of sum_i c_i sqrt(A_i).
+    rng = _rng(42)
+    for _ in range(100):
+        tc, pc, om = rng.uniform(190, 620), rng.uniform(2e6, 5e6), rng.uniform(0.01, 0.5)
+        Tc = np.array([tc, tc, rng.uniform(190, 620)])
+        Pc = np.array([pc, pc, rng.uniform(2e6, 5e6)])
+        omega = np.array([om, om, rng.uniform(0.01, 0.5)])
+        k = rng.uniform(0.0, 0.15)
+        kij = np.zeros((3, 3))
+        kij[0, 1] = kij[1, 0] = k
+        T, P = rng.uniform(200, 600), rng.uniform(1e5, 2e7)
+        c = rng.dirichlet([1, 1, 1])
+        cs = c[[1, 0, 2]]
+        l1, i1 = orc.lnphi(Tc, Pc, omega, kij, T, P, c)
+        l2, i2 = orc.lnphi(Tc, Pc, omega, kij, T, P, cs)
+        assert abs(i1["A"] - i2["A"]) <= 1e-14 * i1["A"]
+        if i1["Z"] == i2["Z"]:
+            assert np.allclose(l1[[1, 0, 2]], l2, rtol=0, atol=1e-12)
+        # k = 0: A = (sum c_i sqrt(A_i))^2 with A_i the pure values
+        _, i0 = orc.lnphi(Tc, Pc, omega, np.zeros((3, 3)), T, P, c)
+        Ai = []
+        for j in range(3):
+            e = np.full(3, 1e-300)
+            e[j] = 1.0
+            Ai.append(orc.lnphi(Tc, Pc, omega, np.zeros((3, 3)), T, P, e)[1]["A"])
+        assert abs(i0["A"] - np.dot(c, np.sqrt(Ai)) ** 2) <= 1e-13 * i0["A"]

@@ -159,6 +159,41 @@ def test_binary_label_matches_tpd_grid_search(orc):
     assert agree == tested
 
 
+def test_binary_min_tpd_is_the_grid_minimum(orc):
+    # The label rule's min TPD (the triage tpd values and tpd at every
+    # non-trivial stationary point of the two trials run to full
+    # stationarity) against brute force: where the global minimum of
+    # tpd(w) over w1 in (0, 1) is non-trivial (negative, away from w = z),
+    # the two trials reach it and min_tpd equals it; where the global
+    # minimum is the trivial point (tpd(z) = 0, a stable feed), every
+    # candidate of min_tpd is a positive tpd (or there is none: +inf).
+    grid = np.concatenate([np.logspace(-12, -2, 200), np.linspace(0.01, 0.99, 1500),
+                           1 - np.logspace(-2, -12, 200)])
+    neg = pos = 0
+    for Tc, Pc, om, k, z, T, P in _binary_cases(14, 160):
+        r = orc.flash(_wl(Tc, Pc, om, k, z, T, P), want_min_tpd=1)
+        mt = float(r["min_tpd"][0])
+        f = lambda w: orc.tpd(Tc, Pc, om, k, T, P, z, [w, 1 - w])
+        t = np.array([f(w) for w in grid])
+        j = int(np.argmin(t))
+        a, b = grid[max(j - 1, 0)], grid[min(j + 1, len(grid) - 1)]
+        for _ in range(80):      # golden-section refinement
+            c1, c2 = b - 0.618 * (b - a), a + 0.618 * (b - a)
+            if f(c1) < f(c2):
+                b = c2
+            else:
+                a = c1
+        wmin = 0.5 * (a + b)
+        tmin = min(t.min(), f(wmin))
+        if tmin < -1e-7 and abs(np.log(wmin / z[0])) > 1e-3:
+            neg += 1
+            assert abs(mt - tmin) <= 1e-9 * max(1.0, abs(tmin)), (mt, tmin, z, T, P)
+        elif tmin > -1e-12:
+            pos += 1
+            assert mt > 0.0, (mt, tmin, z, T, P)
+    assert neg > 30 and pos > 30
+
+
 def test_binary_tie_line_independent_of_feed(orc):
     # Gibbs phase rule: at fixed T, P a binary two-phase region has a single
     # tie line, so feeds along it give the same x, y and beta obeys the lever
