@@ -7,7 +7,7 @@ factor) + implicit-function backward; `plain_form` times the plain
 one-launch-per-stage-iteration form on the same inputs.
 
   python bench.py [--steps K] [--warmup W]
-                  [--workload nc8_1m|nc3_10k|nc10_1m|nc20_8m|cs2_10m|cs4_5m|cs9_1m|ragged_4m]
+                  [--workload nc8_1m|nc3_10k|nc10_1m|nc20_8m|c5_8m|cs2_10m|cs4_5m|cs9_1m|ragged_4m]
                   [--form persistent|plain] [--no-cpu-baseline] [--no-adjoint]
                   [--plain-steps N] [--graph]
 
@@ -59,38 +59,73 @@ def _counters(workload: str) -> dict:
     return t
 
 
-def cpu_baseline(w, budget_s: float = 12.0):
-    """The oracle, as it stands, on a bounded leading sample of the workload,
-    on the host's cores."""
-    import oracle
-    threads = min(16, os.cpu_count() or 1)
-    chunk = 20_000
-    done, t0 = 0, time.perf_counter()
-    while done < w.n and time.perf_counter() - t0 < budget_s:
-        sub = w.subset(np.arange(done, min(done + chunk, w.n)))
-        oracle.flash(sub, threads=threads)
-        done += sub.n
-    dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "flashes/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {done} mixtures of {w.name} ({dt:.1f} s wall)"}
+def _cpu_model() -> str | None:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
-def cpu_baseline_ragged(w, budget_s: float = 12.0):
-    """The oracle on a bounded leading sample of a ragged workload, one call
-    per nc present in each chunk."""
+def _oracle_rate(run, n: int, threads: int, target_s: float):
+    """Oracle flashes/s on the first k mixtures with `threads` threads: one
+    warm-up on a short leading sample sizes k so that one run takes about
+    target_s, then the median of three timed runs over the same k."""
+    k0 = min(n, 2000 * threads)
+    t0 = time.perf_counter()
+    run(k0, threads)
+    rate0 = k0 / max(time.perf_counter() - t0, 1e-6)
+    k = int(min(n, max(k0, rate0 * target_s)))
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        run(k, threads)
+        ts.append(time.perf_counter() - t0)
+    dt = float(np.median(ts))
+    return k / dt, k, dt
+
+
+def _cpu_baseline(name: str, n: int, run, target_s: float = 2.5) -> dict:
+    """The oracle, as it stands, on bounded leading samples of the workload:
+    on the host cores of this process (at most 16, one GPU's share of the
+    host) and on one core (the paper's comparison ran single-core, Sec. 5),
+    each the median of three runs after a warm-up."""
+    avail = len(os.sched_getaffinity(0))
+    threads = max(1, min(16, avail))
+    v, k, dt = _oracle_rate(run, n, threads, target_s)
+    v1, k1, dt1 = _oracle_rate(run, n, 1, target_s)
+    return {"value": v, "unit": "flashes/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {k} mixtures of {name}, median of 3 runs after a warm-up "
+                      f"({dt:.2f} s each)",
+            "one_core": {"value": v1, "unit": "flashes/s", "cores": 1,
+                         "sample": f"first {k1} mixtures of {name}, median of 3 runs "
+                                   f"after a warm-up ({dt1:.2f} s each)"},
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(), "affinity": avail}
+
+
+def cpu_baseline(w) -> dict:
     import oracle
-    threads = min(16, os.cpu_count() or 1)
-    chunk = 20_000
-    done, t0 = 0, time.perf_counter()
-    while done < w.n and time.perf_counter() - t0 < budget_s:
-        idx = np.arange(done, min(done + chunk, w.n))
+
+    def run(k, threads):
+        oracle.flash(w.subset(np.arange(k)), threads=threads)
+
+    return _cpu_baseline(w.name, w.n, run)
+
+
+def cpu_baseline_ragged(w) -> dict:
+    """As cpu_baseline, one oracle call per nc present in the sample."""
+    import oracle
+
+    def run(k, threads):
+        idx = np.arange(k)
         for nc in np.unique(w.nc_of[idx]):
             _, sub = w.select(idx[w.nc_of[idx] == nc], int(nc))
             oracle.flash(sub, threads=threads)
-        done += len(idx)
-    dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "flashes/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {done} mixtures of {w.name} ({dt:.1f} s wall)"}
+
+    return _cpu_baseline(w.name, w.n, run)
 
 
 def bench_ragged(args):
@@ -189,6 +224,9 @@ def main():
         return
     makers = {"nc8_1m": workloads.nc8_workload, "nc3_10k": workloads.nc3_workload,
               "nc10_1m": workloads.nc10_workload, "nc20_8m": workloads.nc20_workload,
+              # the hard-case Nc = 20 workload: 30 % within 2 % of the phase
+              # boundary (needs the cache written by tests/c5_boundary.py)
+              "c5_8m": workloads.c5_workload,
               # the paper's case studies at its largest sizes (Sec. 5.1)
               "cs2_10m": lambda: workloads.case_study_workload("cs2", 10_000_000),
               "cs4_5m": lambda: workloads.case_study_workload("cs4", 5_000_000),

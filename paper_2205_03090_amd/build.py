@@ -1,7 +1,8 @@
 """Builds the gfx950 HIP library in-tree with hipcc.
 
-The flash kernels are instantiated per component count: `csrc/flash_nc.hip`
-is compiled once for every nc in [2, MAX_NC] (in parallel), `csrc/ptflash.hip`
+The flash kernels are instantiated per component count and layout of the
+component sets: `csrc/flash_nc.hip` is compiled once for every nc in
+[2, MAX_NC] and each layout (in parallel), `csrc/ptflash.hip`
 holds the C ABI, and the objects are linked into `lib/libptflash.so`.
 """
 from __future__ import annotations
@@ -50,9 +51,10 @@ def compile_commands() -> list[tuple[list[str], str]]:
     """(command, object) for every translation unit."""
     cmds = []
     for nc in range(MIN_NC, MAX_NC + 1):
-        obj = os.path.join(OBJDIR, f"flash_nc{nc}.o")
-        cmds.append((["hipcc", *FLAGS, *nc_flags(nc), f"-DPTF_NC={nc}", "-c",
-                      os.path.join(CSRC, "flash_nc.hip"), "-o", obj], obj))
+        for pm in (0, 1):
+            obj = os.path.join(OBJDIR, f"flash_nc{nc}_pm{pm}.o")
+            cmds.append((["hipcc", *FLAGS, *nc_flags(nc), f"-DPTF_NC={nc}", f"-DPTF_PM={pm}",
+                          "-c", os.path.join(CSRC, "flash_nc.hip"), "-o", obj], obj))
     obj = os.path.join(OBJDIR, "ptflash.o")
     cmds.append((["hipcc", *FLAGS, "-c", os.path.join(CSRC, "ptflash.hip"), "-o", obj], obj))
     return cmds
@@ -72,7 +74,7 @@ def build(verbose: bool = False) -> str:
         return obj
 
     # the large component counts take longest: start them first
-    order = sorted(cmds, key=lambda c: -int(c[1].rsplit("nc", 1)[-1][:-2])
+    order = sorted(cmds, key=lambda c: -int(c[1].rsplit("nc", 1)[-1].split("_")[0])
                    if "flash_nc" in c[1] else 0)
     with cf.ThreadPoolExecutor(_jobs()) as ex:
         objs = list(ex.map(run, order))

@@ -49,15 +49,16 @@ struct BwdArgs {
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Per-nc launchers (flash_launch.hpp).  props_per_mixture selects the
-// kernels that read one component set per mixture.
+// Per-nc launchers (flash_launch.hpp).  PM (props_per_mixture) selects the
+// kernels that read one component set per mixture; the two layouts are
+// instantiated in separate translation units.
 template <int NC>
 size_t nc_workspace_bytes(int64_t n, int form);
-template <int NC>
-int nc_flash(const FlashArgs &a, const ptflash_problem *p, const ptflash_options *o, void *ws,
-             hipStream_t s);
-template <int NC>
-int nc_backward(const BwdArgs &b, const ptflash_problem *p, hipStream_t s);
+template <int NC, bool PM>
+int nc_flash_pm(const FlashArgs &a, const ptflash_problem *p, const ptflash_options *o, void *ws,
+                hipStream_t s);
+template <int NC, bool PM>
+int nc_backward_pm(const BwdArgs &b, const ptflash_problem *p, hipStream_t s);
 template <int NC>
 int nc_eval(int64_t n, const double *c, const double *T, const double *P, const double *Tc,
             const double *Pc, const double *om, const double *K, double *lnphi, double *Z,

@@ -265,13 +265,13 @@ __device__ __forceinline__ double hv_g(const double (&hrow)[NC], double dadd, do
 // Trust-region step of Hebden type across the group: as trust_step, with
 // this lane's entries of u and g, row of M and diagonal term (H = M +
 // diag(dadd), M_ii = hdiag); lrow/dinv hold this lane's row of the last
-// factor, the LDS the whole factor.
+// factor, the LDS the whole factor.  newton_only as in trust_step.
 template <int NC, int G>
 __device__ __forceinline__ double trust_step_g(double &u, double &radius, bool &eta0,
                                                double (&lrow)[NC], double &dinv,
                                                const double (&hrow)[NC], double hdiag,
                                                double dadd, double gv, const Grp<NC, G> &g,
-                                               uint32_t &fl)
+                                               uint32_t &fl, bool newton_only = false)
 {
     const double mg = -gv;
     eta0 = false;
@@ -296,6 +296,7 @@ __device__ __forceinline__ double trust_step_g(double &u, double &radius, bool &
     } else if (!(radius > 0.0)) {
         radius = 1.0;
     }
+    if (newton_only) return 0.0;
     if (!have) {
         double rs = 0.0;
 #pragma unroll
@@ -370,6 +371,7 @@ struct SaTrGroup {
     int t;
     double lw, lacc, d, s, b;   // this lane's component
     double rad, facc, pred, gacc, zw;
+    double slen;   // length of the last step taken, in the region's norm
     bool pend;
     int tr, steps;
     uint32_t fl, st;
@@ -432,15 +434,17 @@ struct SaTrGroup {
                 ratio = (tm - facc) / pred;
                 accept = (tm < facc) && ratio > 0.0;
             }
+            // a rejected or poor step halves the radius, from the length of
+            // the step taken when the boundary cut made it shorter
             if (!accept) {
-                rad *= 0.5;
+                rad = 0.5 * fmin(rad, slen);
                 lw = lacc;
                 if (++steps < kStepGuard) return false;   // re-evaluate there
                 st |= kStSaUnconv;
                 done(c, facc, g);
                 return true;
             }
-            if (ratio <= 0.25) rad *= 0.5;
+            if (ratio <= 0.25) rad = 0.5 * fmin(rad, slen);
             else if (ratio >= 0.75) rad *= 2.0;
         }
         if (tm < -a.eps_tm || gmx < a.tol_sa_tr) {
@@ -465,6 +469,7 @@ struct SaTrGroup {
         double pr = trust_step_g<NC, G>(u, rad, eta0, lrow, dinv, hrow, hdiag, dadd, gv, g, fl);
         const double bi = 2.0 * sqrt(W);
         const double amax = gmin<G>((g.act && u < 0.0) ? fmin(1.0, 0.99 * bi / -u) : 1.0);
+        slen = amax * sqrt(gsum<G>(g.act ? u * u : 0.0));
         if (amax < 1.0) {
             const double gu = gsum<G>(gv * u);
             pr = amax * gu + amax * amax * (pr - gu);
@@ -495,6 +500,8 @@ struct SpNtGroup {
     int64_t m;
     double z, v0, v1, s, b;   // this lane's component
     double srad, sfacc, spred, sgacc, sdprev, zx, zy;
+    double slen;   // scaled length of the last trust-region step taken
+    bool tronly;   // refinement found H indefinite: take a trust-region step first
     bool spend, spol;
     int tr, pol, steps;
     uint32_t fl, status;
@@ -516,7 +523,7 @@ struct SpNtGroup {
         fl = r.fl;
         status = r.status;
         srad = 0.0;
-        spend = spol = false;
+        spend = spol = tronly = false;
         tr = pol = steps = 0;
         zx = zy = -1.0;
         return true;
@@ -655,29 +662,52 @@ struct SpNtGroup {
                 ratio = (G_ - sfacc) / spred;
                 accept = (G_ < sfacc) && ratio > 0.0;
             }
+            // a rejected or poor step halves the radius, from the length of
+            // the step taken when the boundary cut made it shorter
             if (!accept) {
-                srad *= 0.5;
+                srad = 0.5 * fmin(srad, slen);
                 v0 = v1;
                 if (++steps < kStepGuard) return false;   // re-evaluate there
                 status |= kStSplitUnconv | kStStepCap;
                 finish(c, g, Z0, o.Z, false, vs);
                 return true;
             }
-            if (ratio <= 0.25) srad *= 0.5;
+            if (ratio <= 0.25) srad = 0.5 * fmin(srad, slen);
             else if (ratio >= 0.75) srad *= 2.0;
         }
-        if (!spol && gmx < a.tol_split_tr) {
+        if (!spol && !tronly && gmx < a.tol_split_tr) {
             spol = true;   // the paper's criterion holds: refine
             sdprev = 1e300;
         }
+        // One call site for both the refinement's Newton step and the
+        // trust-region step (as SpNtItem).  Newton refinement runs while H is
+        // positive definite; an indefinite H sends the split back to the
+        // trust region, which starts from the same point at the next step.
+        const bool newton = spol;
+        if (!newton) {
+            if (tr >= a.max_tr_split || ++steps >= kStepGuard) {
+                status |= kStSplitUnconv;
+                finish(c, g, Z0, o.Z, false, vs);
+                return true;
+            }
+            status |= kStSplitTr;
+        }
         double u;
         bool eta0;
-        if (spol) {
-            // Newton refinement while H is positive definite; an indefinite H
-            // sends the split back to the trust region
-            double rad = 1e300;
-            trust_step_g<NC, G>(u, rad, eta0, lrow, dinv, hrow, hdiag, dadd, gs, g, fl);
-            if (!eta0) spol = false;
+        double rad = newton ? 1e300 : srad;
+        double pr = trust_step_g<NC, G>(u, rad, eta0, lrow, dinv, hrow, hdiag, dadd, gs, g, fl,
+                                        newton);
+        if (newton && !eta0) {
+            spol = false;
+            tronly = true;
+            if (++steps < kStepGuard) return false;
+            status |= kStSplitUnconv;
+            finish(c, g, Z0, o.Z, false, vs);
+            return true;
+        }
+        if (!newton) {
+            srad = rad;
+            tronly = false;
         }
         if (spol) {
             u *= vs;
@@ -698,14 +728,8 @@ struct SpNtGroup {
             ++pol;
             return false;
         }
-        if (tr >= a.max_tr_split || ++steps >= kStepGuard) {
-            status |= kStSplitUnconv;
-            finish(c, g, Z0, o.Z, false, vs);
-            return true;
-        }
-        status |= kStSplitTr;
-        double pr = trust_step_g<NC, G>(u, srad, eta0, lrow, dinv, hrow, hdiag, dadd, gs, g, fl);
         // dn = v o u, kept inside 0 < n^V < z
+        const double nu = sqrt(gsum<G>(g.act ? u * u : 0.0));
         u *= vs;
         double lim = 1.0;
         if (g.act && u < 0.0) lim = fmin(lim, 0.99 * v0 / -u);
@@ -715,6 +739,7 @@ struct SpNtGroup {
             const double gu = gsum<G>(gt * u);
             pr = amax * gu + amax * amax * (pr - gu);
         }
+        slen = amax * nu;
         v1 = v0;
         v0 += amax * u;
         fl += 6 * NC;

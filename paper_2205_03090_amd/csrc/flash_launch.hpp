@@ -90,6 +90,56 @@ __device__ __forceinline__ unsigned long long bcast64(unsigned long long v, int 
     return ((unsigned long long)hi << 32) | lo;
 }
 
+// Input positions a wavefront takes from its stage's input.  First its
+// static share, a contiguous range of three quarters of the input split
+// evenly (consecutive lanes take consecutive positions, which keeps the
+// mixtures a wavefront touches, and the records it reads, close together in
+// memory); then chunks of kChunk positions from the stage's counter, one
+// atomic per chunk.
+struct Claim {
+    unsigned long long nw, wid, s0, sj, dyn0, cb, ce;   // [cb, ce): claimed, not yet taken
+
+    __device__ __forceinline__ Claim(int64_t count, unsigned long long nw_,
+                                     unsigned long long wid_)
+        : nw(nw_), wid(wid_), sj(0), cb(0), ce(0)
+    {
+        s0 = (unsigned long long)(count > 0 ? count : 0) * 3ull / 4ull / nw;
+        dyn0 = nw * s0;
+    }
+
+    // Called by every lane of the wavefront with the number r (1..64) of
+    // takers; returns the position for the taker of rank `rank` (used in
+    // the taker lanes only).
+    __device__ __forceinline__ unsigned long long next(int r, unsigned long long rank, int lane,
+                                                       unsigned long long *take)
+    {
+        const unsigned long long ru = (unsigned long long)r;
+        const unsigned long long as = s0 - sj, ad = ce - cb;
+        unsigned long long nb = 0;
+        if (as + ad < ru) {
+            if (lane == 0) nb = dyn0 + atomicAdd(take, (unsigned long long)kChunk);
+            nb = bcast64(nb, 0);
+        }
+        unsigned long long k;
+        if (rank < as) k = wid * s0 + sj + rank;
+        else if (rank - as < ad) k = cb + (rank - as);
+        else k = nb + (rank - as - ad);
+        if (ru <= as) {
+            sj += ru;
+        } else {
+            sj = s0;
+            const unsigned long long rem = ru - as;
+            if (rem <= ad) {
+                cb += rem;
+            } else {
+                cb = nb + (rem - ad);
+                ce = nb + kChunk;
+            }
+        }
+        return k;
+    }
+};
+
 // Copies a wavefront's staged entries of one list to the global list: one
 // atomic for the whole batch, then a coalesced copy.
 __device__ __forceinline__ void flush_list(const Lists &L, int list, const uint32_t *buf,
@@ -148,8 +198,8 @@ __device__ __forceinline__ void append_slot(const Lists &L, int list, int l, uin
 }
 
 // Persistent stage: one item per lane; lanes whose item finished take the
-// next ids of the wavefront's claimed range: first a static share, then
-// chunks of kChunk ids from the stage's counter (one atomic per chunk).  The
+// next input positions of the wavefront (Claim: a static share, then
+// chunks of kChunk from the stage's counter).  The
 // list entries the steps produce are staged per wavefront in LDS and
 // appended kStage at a time (one atomic per batch).  Every item finishes
 // within its stage's iteration caps (and kStepGuard steps), so every
@@ -170,38 +220,19 @@ stage_persistent(Ctx<NC> c, const double *__restrict__ Tc, const double *__restr
     int fill[NOUT];
 #pragma unroll
     for (int l = 0; l < NOUT; ++l) fill[l] = 0;
-    // static first share of this wavefront: [wid*s0, (wid+1)*s0); the shared
-    // counter hands out ids from nw*s0 on
-    const unsigned long long nw = (unsigned long long)gridDim.x * (blockDim.x / 64);
-    const unsigned long long wid =
-        (unsigned long long)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
-    const unsigned long long s0 = (unsigned long long)(count > 0 ? count : 0) * 3ull / 4ull / nw;
-    const unsigned long long dyn0 = nw * s0;
-    unsigned long long cb = wid * s0, ce = cb + s0;   // claimed, not yet taken: [cb, ce)
+    Claim cl(count, (unsigned long long)gridDim.x * (blockDim.x / 64),
+             (unsigned long long)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64);
     Item it;
     bool live = false, gone = false;
     for (;;) {
         const bool want = !live && !gone;
         const unsigned long long mask = __ballot(want);
         if (mask) {
-            const int r = __popcll(mask);
-            const unsigned long long avail = ce - cb;
-            unsigned long long nb = 0;
-            if (avail < (unsigned long long)r) {
-                if (lane == 0) nb = dyn0 + atomicAdd(take, (unsigned long long)kChunk);
-                nb = bcast64(nb, 0);
-            }
+            const unsigned long long rank = (unsigned long long)__popcll(mask & lanes_below(lane));
+            const unsigned long long k = cl.next(__popcll(mask), rank, lane, take);
             if (want) {
-                const unsigned long long rank = (unsigned long long)__popcll(mask & lanes_below(lane));
-                const unsigned long long k = rank < avail ? cb + rank : nb + (rank - avail);
                 if ((int64_t)k < count) live = it.begin(c, stage_id<Item, NC>(c, (int64_t)k));
                 else gone = true;
-            }
-            if (avail < (unsigned long long)r) {
-                cb = nb + ((unsigned long long)r - avail);
-                ce = nb + kChunk;
-            } else {
-                cb += (unsigned long long)r;
             }
         }
         if (__ballot(!gone) == 0ull) break;
@@ -247,37 +278,20 @@ stage_persistent_group(Ctx<NC> c, const double *__restrict__ Tc, const double *_
     g.act = g.gi < NC;
     g.row = g.act ? g.gi : NC;
     g.sh = group_lds[threadIdx.x / G];
-    const unsigned long long nw = (unsigned long long)gridDim.x * (blockDim.x / 64);
-    const unsigned long long wid =
-        (unsigned long long)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
-    const unsigned long long s0 = (unsigned long long)(count > 0 ? count : 0) * 3ull / 4ull / nw;
-    const unsigned long long dyn0 = nw * s0;
-    unsigned long long cb = wid * s0, ce = cb + s0;   // claimed, not yet taken: [cb, ce)
+    Claim cl(count, (unsigned long long)gridDim.x * (blockDim.x / 64),
+             (unsigned long long)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64);
     Item it;
     bool live = false, gone = false;   // the same in every lane of a group
     for (;;) {
         const bool want = !live && !gone;
         const unsigned long long mask = __ballot(want && g.gi == 0);
         if (mask) {
-            const int r = __popcll(mask);
-            const unsigned long long avail = ce - cb;
-            unsigned long long nb = 0;
-            if (avail < (unsigned long long)r) {
-                if (lane == 0) nb = dyn0 + atomicAdd(take, (unsigned long long)kChunk);
-                nb = bcast64(nb, 0);
-            }
+            const unsigned long long rank =
+                (unsigned long long)__popcll(mask & lanes_below(g.base));
+            const unsigned long long k = cl.next(__popcll(mask), rank, lane, take);
             if (want) {
-                const unsigned long long rank =
-                    (unsigned long long)__popcll(mask & lanes_below(g.base));
-                const unsigned long long k = rank < avail ? cb + rank : nb + (rank - avail);
                 if ((int64_t)k < count) live = it.begin(c, stage_id<Item, NC>(c, (int64_t)k), g);
                 else gone = true;
-            }
-            if (avail < (unsigned long long)r) {
-                cb = nb + ((unsigned long long)r - avail);
-                ce = nb + kChunk;
-            } else {
-                cb += (unsigned long long)r;
             }
         }
         if (__ballot(!gone) == 0ull) break;
@@ -761,27 +775,20 @@ size_t nc_workspace_bytes(int64_t n, int form)
     return workspace_bytes<NC>(n, form);
 }
 
-template <int NC>
-int nc_flash(const FlashArgs &a, const ptflash_problem *p, const ptflash_options *o, void *ws,
-             hipStream_t s)
+template <int NC, bool PM>
+int nc_flash_pm(const FlashArgs &a, const ptflash_problem *p, const ptflash_options *o, void *ws,
+                hipStream_t s)
 {
-    if (o->form == PTFLASH_FORM_PLAIN)
-        return p->props_per_mixture ? launch_plain<NC, true>(a, p, ws, s)
-                                    : launch_plain<NC, false>(a, p, ws, s);
-    return p->props_per_mixture ? launch_persistent<NC, true>(a, p, o, ws, s)
-                                : launch_persistent<NC, false>(a, p, o, ws, s);
+    if (o->form == PTFLASH_FORM_PLAIN) return launch_plain<NC, PM>(a, p, ws, s);
+    return launch_persistent<NC, PM>(a, p, o, ws, s);
 }
 
-template <int NC>
-int nc_backward(const BwdArgs &b, const ptflash_problem *p, hipStream_t s)
+template <int NC, bool PM>
+int nc_backward_pm(const BwdArgs &b, const ptflash_problem *p, hipStream_t s)
 {
     const unsigned nb = (unsigned)((p->n + kBlock - 1) / kBlock);
-    if (p->props_per_mixture)
-        hipLaunchKernelGGL((flash_backward_kernel<NC, true>), dim3(nb), dim3(kBlock), 0, s, b,
-                           p->Tc, p->Pc, p->omega, p->kij);
-    else
-        hipLaunchKernelGGL((flash_backward_kernel<NC, false>), dim3(nb), dim3(kBlock), 0, s, b,
-                           p->Tc, p->Pc, p->omega, p->kij);
+    hipLaunchKernelGGL((flash_backward_kernel<NC, PM>), dim3(nb), dim3(kBlock), 0, s, b, p->Tc,
+                       p->Pc, p->omega, p->kij);
     return hipGetLastError() == hipSuccess ? PTFLASH_OK : PTFLASH_EHIP;
 }
 

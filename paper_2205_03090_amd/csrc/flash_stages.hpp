@@ -40,6 +40,8 @@
 //     below tol_polish, and y is chosen as the phase with the larger Z.
 #pragma once
 
+#include <lane_value.hpp>   // angle brackets: a host build of the items substitutes its own
+
 #include "flash_api.hpp"
 #include "srk_device.hpp"
 
@@ -122,10 +124,7 @@ __device__ __forceinline__ Props mix_props(const Props &pr, int64_t m)
 {
     if constexpr (!PM) {
         if constexpr (NC >= kVectorKFromNc) {
-            // the empty asm makes the pointer a per-lane (VGPR) value
-            uintptr_t k = (uintptr_t)pr.K;
-            __asm__ volatile("" : "+v"(k));
-            return Props{pr.Tc, pr.Pc, pr.om, (const double *)k};
+            return Props{pr.Tc, pr.Pc, pr.om, (const double *)per_lane((uintptr_t)pr.K)};
         } else {
             return pr;
         }
@@ -635,6 +634,7 @@ struct SaTrItem {
     double lw[NC], lacc[NC], d[NC];
     Eos<NC> e;
     double rad, facc, pred, gacc, zw;   // zw: Z of the previous evaluation
+    double slen;   // length of the last step taken, in the region's norm
     bool pend;
     int tr, steps;
     uint32_t fl, st;
@@ -705,8 +705,10 @@ struct SaTrItem {
                 ratio = (tm - facc) / pred;
                 accept = (tm < facc) && ratio > 0.0;
             }
+            // a rejected or poor step halves the radius, from the length of
+            // the step taken when the boundary cut made it shorter
             if (!accept) {
-                rad *= 0.5;
+                rad = 0.5 * fmin(rad, slen);
 #pragma unroll
                 for (int i = 0; i < NC; ++i) lw[i] = lacc[i];
                 if (++steps < kStepGuard) return false;   // re-evaluate there
@@ -714,7 +716,7 @@ struct SaTrItem {
                 done(c, facc);
                 return true;
             }
-            if (ratio <= 0.25) rad *= 0.5;
+            if (ratio <= 0.25) rad = 0.5 * fmin(rad, slen);
             else if (ratio >= 0.75) rad *= 2.0;
         }
         if (tm < -a.eps_tm || gmax < a.tol_sa_tr) {
@@ -746,6 +748,7 @@ struct SaTrItem {
             const double bi = 2.0 * sqrt(W[i]);
             if (u[i] < 0.0) amax = fmin(amax, 0.99 * bi / -u[i]);
         }
+        slen = amax * norm2<NC>(u);
         if (amax < 1.0) {
             double gu = 0.0;
 #pragma unroll
@@ -972,7 +975,9 @@ struct SpNtItem {
     double z[NC], v0[NC], v1[NC];
     Eos<NC> e;
     double srad, sfacc, spred, sgacc, sdprev, zx, zy;   // zx, zy: previous Z
+    double slen;   // scaled length of the last trust-region step taken
     bool spend, spol;
+    bool tronly;   // refinement found H indefinite: take a trust-region step first
     int tr, pol, steps;
     uint32_t fl, status;
 
@@ -990,7 +995,7 @@ struct SpNtItem {
         fl = r.fl;
         status = r.status;
         srad = 0.0;
-        spend = spol = false;
+        spend = spol = tronly = false;
         tr = pol = steps = 0;
         zx = zy = -1.0;
         return true;
@@ -1124,8 +1129,10 @@ struct SpNtItem {
                 ratio = (G - sfacc) / spred;
                 accept = (G < sfacc) && ratio > 0.0;
             }
+            // a rejected or poor step halves the radius, from the length of
+            // the step taken when the boundary cut made it shorter
             if (!accept) {
-                srad *= 0.5;
+                srad = 0.5 * fmin(srad, slen);
 #pragma unroll
                 for (int i = 0; i < NC; ++i) v0[i] = v1[i];
                 if (++steps < kStepGuard) return false;   // re-evaluate there
@@ -1133,21 +1140,42 @@ struct SpNtItem {
                 finish(c, Z0, o.Z, F, false, vs);
                 return true;
             }
-            if (ratio <= 0.25) srad *= 0.5;
+            if (ratio <= 0.25) srad = 0.5 * fmin(srad, slen);
             else if (ratio >= 0.75) srad *= 2.0;
         }
-        if (!spol && gmax < a.tol_split_tr) {
+        if (!spol && !tronly && gmax < a.tol_split_tr) {
             spol = true;   // the paper's criterion holds: refine
             sdprev = 1e300;
         }
+        // One call site for both the refinement's Newton step and the
+        // trust-region step, so that lanes in either mode factor together.
+        // Newton refinement runs while H is positive definite; an indefinite
+        // H sends the split back to the trust region, which starts from the
+        // same point at the next step.
+        const bool newton = spol;
+        if (!newton) {
+            if (tr >= a.max_tr_split || ++steps >= kStepGuard) {
+                status |= kStSplitUnconv;
+                finish(c, Z0, o.Z, F, false, vs);
+                return true;
+            }
+            status |= kStSplitTr;
+        }
         double u[NC];
         bool eta0;
-        if (spol) {
-            // Newton refinement while H is positive definite; an indefinite H
-            // sends the split back to the trust region
-            double rad = 1e300;
-            trust_step<NC>(u, rad, eta0, F, dinv, Hs, gs, fl);
-            if (!eta0) spol = false;
+        double rad = newton ? 1e300 : srad;
+        double pr = trust_step<NC>(u, rad, eta0, F, dinv, Hs, gs, fl, newton);
+        if (newton && !eta0) {
+            spol = false;
+            tronly = true;
+            if (++steps < kStepGuard) return false;
+            status |= kStSplitUnconv;
+            finish(c, Z0, o.Z, F, false, vs);
+            return true;
+        }
+        if (!newton) {
+            srad = rad;
+            tronly = false;
         }
         if (spol) {
             double dmax = 0.0, amax = 1.0;
@@ -1173,14 +1201,8 @@ struct SpNtItem {
             ++pol;
             return false;
         }
-        if (tr >= a.max_tr_split || ++steps >= kStepGuard) {
-            status |= kStSplitUnconv;
-            finish(c, Z0, o.Z, F, false, vs);
-            return true;
-        }
-        status |= kStSplitTr;
-        double pr = trust_step<NC>(u, srad, eta0, F, dinv, Hs, gs, fl);
         // dn = v o u, kept inside 0 < n^V < z
+        const double nu = norm2<NC>(u);
         double amax = 1.0;
 #pragma unroll
         for (int i = 0; i < NC; ++i) {
@@ -1194,6 +1216,7 @@ struct SpNtItem {
             for (int i = 0; i < NC; ++i) gu += gt[i] * u[i];
             pr = amax * gu + amax * amax * (pr - gu);
         }
+        slen = amax * nu;
 #pragma unroll
         for (int i = 0; i < NC; ++i) {
             v1[i] = v0[i];

@@ -118,7 +118,8 @@ struct FlashF {
     static int run(const FlashArgs &a, const ptflash_problem *p, const ptflash_options *o,
                    void *ws, hipStream_t s)
     {
-        return nc_flash<NC>(a, p, o, ws, s);
+        return p->props_per_mixture ? nc_flash_pm<NC, true>(a, p, o, ws, s)
+                                    : nc_flash_pm<NC, false>(a, p, o, ws, s);
     }
 };
 
@@ -135,7 +136,8 @@ template <int NC>
 struct BackwardF {
     static int run(const BwdArgs &b, const ptflash_problem *p, hipStream_t s)
     {
-        return nc_backward<NC>(b, p, s);
+        return p->props_per_mixture ? nc_backward_pm<NC, true>(b, p, s)
+                                    : nc_backward_pm<NC, false>(b, p, s);
     }
 };
 

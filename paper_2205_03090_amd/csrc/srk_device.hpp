@@ -396,12 +396,15 @@ __device__ __forceinline__ double norm2(const double (&v)[NC])
 // region) is returned.  radius <= 0 on entry asks for the initial radius:
 // ||Newton step|| when H is positive definite, else 1.  Returns the predicted
 // change of the quadratic model g.u + u'Hu/2 (negative) and whether the step
-// is the unshifted Newton step; Lf then holds the factor of H.
+// is the unshifted Newton step; Lf then holds the factor of H.  With
+// newton_only the call stops after the factorisation of H: eta0 tells
+// whether H is positive definite, and u is the Newton step when it is.
 template <int NC>
 __device__ __forceinline__ double trust_step(double (&u)[NC], double &radius, bool &eta0,
                                              double (&Lf)[Tri<NC>::N], double (&dinv)[NC],
                                              const double (&H)[Tri<NC>::N],
-                                             const double (&g)[NC], uint32_t &fl)
+                                             const double (&g)[NC], uint32_t &fl,
+                                             bool newton_only = false)
 {
     double mg[NC], y[NC];
 #pragma unroll
@@ -430,6 +433,7 @@ __device__ __forceinline__ double trust_step(double (&u)[NC], double &radius, bo
     } else if (!(radius > 0.0)) {
         radius = 1.0;
     }
+    if (newton_only) return 0.0;
     if (!have) {
         double hmin = H[0], rowmax = 0.0;
 #pragma unroll

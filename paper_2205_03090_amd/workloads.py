@@ -22,6 +22,7 @@ for the nine-component fluids) are built by ``case_study_workload``.
 """
 from __future__ import annotations
 
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -108,6 +109,61 @@ def nc20_workload(n: int = 8_000_000, seed: int = SEEDS["nc20"]) -> Workload:
     hard-case workload; the boundary-hugging part needs the oracle's labels
     and is built by the tests)."""
     return uniform_workload("nc20_8m", seed, n, 20, 0.3, (200.0, 600.0), (1.0e5, 3.0e7))
+
+
+# The hard-case Nc = 20 workload (30 % of its mixtures within 2 % of a phase
+# boundary in pressure, the rest the uniform draw above).  The boundary
+# pressures come from bisection on the oracle's stability decision, written
+# once by tests/c5_boundary.py to a cache file; this module only redraws the
+# candidates' random numbers and reads that file.
+C5_SEED = 20_250_006
+C5_BLOCK = 1 << 16
+C5_N = 8_000_000
+C5_N_BOUNDARY = 2_400_000
+C5_CACHE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "tests", "data", "c5_boundary_nc20.npz")
+
+
+def c5_candidates(b: int):
+    """Candidate block b of the boundary part: z ~ Dirichlet(0.3 * 1),
+    T ~ U[200, 600] K and the relative offset u ~ U[-0.02, 0.02] of the
+    pressure from the boundary, C5_BLOCK rows each."""
+    rng = np.random.Generator(np.random.PCG64([C5_SEED, b]))
+    z = rng.dirichlet(np.full(20, 0.3), size=C5_BLOCK)
+    T = rng.uniform(200.0, 600.0, C5_BLOCK)
+    u = rng.uniform(-0.02, 0.02, C5_BLOCK)
+    return z, T, u
+
+
+def c5_workload(path: str = C5_CACHE) -> Workload:
+    """Nc = 20, 8,000,000 mixtures, one shared component set (that of
+    nc20_workload): 5,600,000 drawn as nc20_workload and 2,400,000 placed
+    within 2 % of the oracle's phase boundary (P = P_b (1 + u), P_b from the
+    cache file), shuffled together by a seeded permutation."""
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is missing: write it with `python tests/c5_boundary.py`")
+    with np.load(path) as f:
+        block, row, pb = f["block"].astype(np.int64), f["row"].astype(np.int64), f["pb"]
+    if len(pb) != C5_N_BOUNDARY:
+        raise ValueError(f"{path} holds {len(pb)} boundary mixtures, not {C5_N_BOUNDARY}")
+    uni = nc20_workload(n=C5_N - C5_N_BOUNDARY)
+    zb = np.empty((C5_N_BOUNDARY, 20))
+    Tb = np.empty(C5_N_BOUNDARY)
+    Pb = np.empty(C5_N_BOUNDARY)
+    for b in np.unique(block):
+        sel = np.where(block == b)[0]
+        z, T, u = c5_candidates(int(b))
+        zb[sel] = z[row[sel]]
+        Tb[sel] = T[row[sel]]
+        Pb[sel] = pb[sel].astype(np.float64) * (1.0 + u[row[sel]])
+    perm = np.random.Generator(np.random.PCG64(C5_SEED + 1)).permutation(C5_N)
+    z = np.concatenate([uni.z, zb])[perm]
+    T = np.concatenate([uni.T, Tb])[perm]
+    P = np.concatenate([uni.P, Pb])[perm]
+    w = Workload("c5_8m", C5_N, 20, np.ascontiguousarray(z), T, P, uni.Tc, uni.Pc, uni.omega,
+                 uni.kij)
+    w.boundary = perm >= C5_N - C5_N_BOUNDARY   # rows of the boundary part
+    return w
 
 
 def cotangents(seed: int, n: int, nc: int):

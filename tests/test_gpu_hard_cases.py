@@ -12,6 +12,7 @@ import oracle  # noqa: E402
 from paper_2205_03090_amd import _capi, api, workloads  # noqa: E402
 from parity import assert_parity, compare, gpu_to_numpy, invariants  # noqa: E402
 import hard_cases  # noqa: E402
+from adjoint_ref import check_vjp  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 CLEAN = _capi.ST["INVALID"] | _capi.ST["SPLIT_UNCONV"] | _capi.ST["STEP_CAP"]
@@ -53,37 +54,24 @@ def test_uniform_nc20_forward_parity():
 
 
 def _vjp_vs_oracle(w, idx_limit, seed, per_mixture=False):
+    # the reference is the oracle's Jacobian at the oracle's own converged
+    # split, at three finite-difference steps (near a phase boundary the
+    # split is ill-conditioned and their spread estimates the reference's
+    # own error); compared where the GPU's split is the oracle's
     r = api.flash(w.z, w.T, w.P, w.Tc, w.Pc, w.omega, w.kij, keep_factor=True)
     gb, gx, gy = workloads.cotangents(seed, w.n, w.nc)
-    gz, gT, gP, gk = api.flash_backward(w.z, w.T, w.P, w.Tc, w.Pc, w.omega, w.kij, r, gb, gx,
-                                        gy, kij_reduce=False)
+    grads = api.flash_backward(w.z, w.T, w.P, w.Tc, w.Pc, w.omega, w.kij, r, gb, gx, gy,
+                               kij_reduce=False)
     torch.cuda.synchronize()
-    gz, gT, gP, gk = (t.cpu().numpy() for t in (gz, gT, gP, gk))
-    lab, beta, y = r.label.cpu().numpy(), r.beta.cpu().numpy(), r.y.cpu().numpy()
+    grads = tuple(t.cpu().numpy() for t in grads)
+    lab, beta = r.label.cpu().numpy(), r.beta.cpu().numpy()
     st = r.status.cpu().numpy().astype(np.int64) & 0xffff
     two = np.where((lab == 1) & (st & CLEAN == 0) & (beta > 1e-3) & (beta < 1 - 1e-3))[0]
     two = two[:idx_limit]
-    nc = w.nc
-    pairs = [(a, b) for a in range(nc) for b in range(a + 1, nc)]
-    worst = 0.0
-    for m in two:
-        sets = (w.Tc[m], w.Pc[m], w.omega[m], w.kij[m]) if per_mixture else \
-            (w.Tc, w.Pc, w.omega, w.kij)
-        ob = np.concatenate([[gb[m]], gx[m], gy[m]])
-        args = (*sets, w.z[m], w.T[m], w.P[m], beta[m], y[m])
-        # the reference at three finite-difference steps: their spread
-        # estimates its own error (near a phase boundary the split is
-        # ill-conditioned and the differences are far from converged)
-        ref = oracle.flash_jacobian(*args, hrel=1e-3).T @ ob
-        spread = max(np.abs(ref - oracle.flash_jacobian(*args, hrel=h).T @ ob).max()
-                     for h in (3e-3, 3e-4))
-        got = np.concatenate([gz[m], [gT[m], gP[m]],
-                              [gk[m, a, b] + gk[m, b, a] for a, b in pairs]])
-        tol = 1e-7 * np.abs(ref).max() + 10.0 * spread
-        err = np.abs(got - ref).max() / tol
-        worst = max(worst, err)
-        assert err < 1.0, (m, np.abs(got - ref).max(), tol)
-    return len(two), worst
+    ob = np.concatenate([gb[:, None], gx, gy], axis=1)[two]
+    k, worst, other = check_vjp(w, two, gpu_to_numpy(r), grads, ob, spread_h=(3e-3, 3e-4))
+    assert other <= max(1, len(two) // 20)
+    return k, worst
 
 
 def test_boundary_nc20_adjoint_vs_oracle_jacobian(boundary):

@@ -213,8 +213,11 @@ def test_resubmission_of_unconverged_splits():
     fs = full["status"][idx].astype(np.int64)
     ok = (full["label"][idx] == 1) & ((fs & ST["SPLIT_UNCONV"]) == 0)
     assert np.all(again["label"][ok] == 1)
+    # compared where both runs converged: the contract's 1e-10 on every row
+    ok &= (again["status"].astype(np.int64) & ST["SPLIT_UNCONV"]) == 0
+    assert ok.sum() > 0.95 * len(idx)
     err = np.maximum(np.abs(again["beta"][ok] - full["beta"][idx][ok]),
                      np.maximum(np.abs(again["x"][ok] - full["x"][idx][ok]).max(1),
                                 np.abs(again["y"][ok] - full["y"][idx][ok]).max(1)))
     print(f"[re-submission] {len(idx)} unconverged; max err {err.max():.2e}", flush=True)
-    assert np.mean(err < 1e-10) > 0.99 and err.max() < 1e-8
+    assert err.max() < 1e-10
