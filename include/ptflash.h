@@ -282,6 +282,26 @@ int ptflash_flash_ragged(const ptflash_ragged_problem *prob, const ptflash_optio
                          ptflash_result *res, void *workspace, size_t ws_bytes,
                          hipStream_t stream);
 
+/* Largest workspace, in bytes, of ptflash_flash_noalloc: the size of the
+ * library's own device scratch buffer (one per GPU). */
+#define PTFLASH_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* ptflash_flash for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same flash, with the library's own static device scratch buffer of
+ * PTFLASH_NOALLOC_SCRATCH_BYTES bytes as its workspace instead of a
+ * caller's.  The caller still passes inputs and outputs.  No device memory
+ * is allocated or freed by this call (the buffer exists once per GPU, for
+ * the life of the process; its address is looked up on the first call on
+ * each device).  Returns PTFLASH_EWORKSPACE, without launching anything,
+ * when ptflash_workspace_bytes(prob, opt) exceeds the buffer (about 10^5
+ * mixtures at nc = 8, 4.8 * 10^4 at nc = 20, persistent form).  Every call
+ * on one GPU uses that GPU's one buffer: calls that overlap in time on one
+ * GPU (different streams or host threads) race and must not be issued.
+ * Arguments, outputs and other error codes as ptflash_flash. */
+int ptflash_flash_noalloc(const ptflash_problem *prob, const ptflash_options *opt,
+                          ptflash_result *res, hipStream_t stream);
+
 /* Text for a return code (static storage). */
 const char *ptflash_strerror(int code);
 

@@ -20,7 +20,8 @@ ST = dict(INVALID=0x0001, SHORTCUT=0x0002, SA_RAN=0x0004, SA_UNCONV=0x0008,
 EXPORTS = ["ptflash_default_options", "ptflash_max_nc", "ptflash_workspace_bytes",
            "ptflash_flash", "ptflash_flash_backward", "ptflash_backward_workspace_bytes",
            "ptflash_eval_phase", "ptflash_strerror", "ptflash_ragged_workspace_bytes",
-           "ptflash_flash_ragged", "ptflash_stability"]
+           "ptflash_flash_ragged", "ptflash_stability", "ptflash_flash_noalloc"]
+NOALLOC_SCRATCH_BYTES = 64 << 20   # PTFLASH_NOALLOC_SCRATCH_BYTES
 
 _vp = C.c_void_p
 
@@ -74,6 +75,9 @@ def lib():
         L.ptflash_flash.restype = C.c_int
         L.ptflash_stability.argtypes = L.ptflash_flash.argtypes
         L.ptflash_stability.restype = C.c_int
+        L.ptflash_flash_noalloc.argtypes = [C.POINTER(Problem), C.POINTER(Options),
+                                            C.POINTER(Result), _vp]
+        L.ptflash_flash_noalloc.restype = C.c_int
         L.ptflash_backward_workspace_bytes.argtypes = [C.POINTER(Problem), C.c_int32]
         L.ptflash_backward_workspace_bytes.restype = C.c_size_t
         L.ptflash_flash_backward.argtypes = [C.POINTER(Problem), C.POINTER(Options),

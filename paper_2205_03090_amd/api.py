@@ -104,8 +104,31 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
     return buf[off:off + max(int(nbytes), 1)]
 
 
+def _new_result(n, nc, dev, keep_factor):
+    return FlashResult(
+        label=torch.empty(n, dtype=torch.int8, device=dev),
+        beta=torch.empty(n, dtype=torch.float64, device=dev),
+        x=torch.empty((n, nc), dtype=torch.float64, device=dev),
+        y=torch.empty((n, nc), dtype=torch.float64, device=dev),
+        iters=torch.empty((n, _capi.NITERS), dtype=torch.int16, device=dev),
+        status=torch.empty(n, dtype=torch.int16, device=dev),
+        flops=torch.empty(n, dtype=torch.int32, device=dev),
+        factor=(torch.full((n, nc * (nc + 1) // 2), float("nan"), dtype=torch.float64,
+                           device=dev) if keep_factor else None),
+        tm=torch.empty(n, dtype=torch.float64, device=dev))
+
+
+def _result_struct(out: FlashResult):
+    return _capi.Result(label=_ptr(out.label).value, beta=_ptr(out.beta).value,
+                        x=_ptr(out.x).value, y=_ptr(out.y).value, iters=_ptr(out.iters).value,
+                        status=_ptr(out.status).value, flops=_ptr(out.flops).value,
+                        factor=None if out.factor is None else _ptr(out.factor).value,
+                        tm=None if out.tm is None else _ptr(out.tm).value)
+
+
 def flash(z, T, P, Tc, Pc, omega, kij, *, keep_factor: bool = False, stream=None,
-          out: FlashResult | None = None, lnk0=None, hint=None, **opts) -> FlashResult:
+          out: FlashResult | None = None, lnk0=None, hint=None, noalloc: bool = False,
+          **opts) -> FlashResult:
     """Isothermal two-phase SRK flash of n mixtures on the current GPU.
 
     z (n, nc), T (n,), P (n,) and the component set Tc, Pc, omega (nc,), kij
@@ -113,7 +136,9 @@ def flash(z, T, P, Tc, Pc, omega, kij, *, keep_factor: bool = False, stream=None
     lnk0 (n, nc): initial ln K in place of Wilson's; hint (n,)
     int8: 0 known stable, 1 known unstable, else none (ptflash_problem).
     Keyword options override ptflash_default_options (e.g.
-    form=_capi.FORM_PLAIN)."""
+    form=_capi.FORM_PLAIN).  noalloc=True calls ptflash_flash_noalloc (the
+    library's own device scratch as workspace; at most
+    _capi.NOALLOC_SCRATCH_BYTES of it)."""
     dev = torch.device("cuda", torch.cuda.current_device())
     z, T, P = _f64(z, dev), _f64(T, dev), _f64(P, dev)
     Tc, Pc, omega, kij = (_f64(a, dev) for a in (Tc, Pc, omega, kij))
@@ -122,23 +147,15 @@ def flash(z, T, P, Tc, Pc, omega, kij, *, keep_factor: bool = False, stream=None
     o = _capi.default_options(keep_factor=int(keep_factor), **opts)
     prob = make_problem(z, T, P, Tc, Pc, omega, kij, lnk0, hint)
     if out is None:
-        out = FlashResult(
-            label=torch.empty(n, dtype=torch.int8, device=dev),
-            beta=torch.empty(n, dtype=torch.float64, device=dev),
-            x=torch.empty((n, nc), dtype=torch.float64, device=dev),
-            y=torch.empty((n, nc), dtype=torch.float64, device=dev),
-            iters=torch.empty((n, _capi.NITERS), dtype=torch.int16, device=dev),
-            status=torch.empty(n, dtype=torch.int16, device=dev),
-            flops=torch.empty(n, dtype=torch.int32, device=dev),
-            factor=(torch.full((n, nc * (nc + 1) // 2), float("nan"), dtype=torch.float64,
-                               device=dev) if keep_factor else None),
-            tm=torch.empty(n, dtype=torch.float64, device=dev))
-    res = _capi.Result(label=_ptr(out.label).value, beta=_ptr(out.beta).value,
-                       x=_ptr(out.x).value, y=_ptr(out.y).value, iters=_ptr(out.iters).value,
-                       status=_ptr(out.status).value, flops=_ptr(out.flops).value,
-                       factor=None if out.factor is None else _ptr(out.factor).value,
-                       tm=None if out.tm is None else _ptr(out.tm).value)
+        out = _new_result(n, nc, dev, keep_factor)
+    res = _result_struct(out)
     L = _capi.lib()
+    if noalloc:
+        rc = L.ptflash_flash_noalloc(C.byref(prob), C.byref(o), C.byref(res),
+                                     _stream_handle(stream))
+        _capi.check(rc, "ptflash_flash_noalloc")
+        out._keepalive = (z, T, P, Tc, Pc, omega, kij, lnk0, hint)
+        return out
     ws_bytes = L.ptflash_workspace_bytes(C.byref(prob), C.byref(o))
     ws = _workspace(ws_bytes, dev)
     rc = L.ptflash_flash(C.byref(prob), C.byref(o), C.byref(res), _ptr(ws), ws_bytes,

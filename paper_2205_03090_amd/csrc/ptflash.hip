@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "ptflash.h"
 #include "flash_api.hpp"
@@ -66,6 +67,31 @@ reduce_pairs_final(const double *__restrict__ part, int64_t nchunk, int nc, doub
 }
 
 static int64_t red_chunks(int64_t n) { return (n + kRedChunk - 1) / kRedChunk; }
+
+// Workspace of ptflash_flash_noalloc: a static device array (one copy on
+// every GPU the library runs on, kept until the process ends).  Its name is
+// a host-side stand-in; the device address comes from hipGetSymbolAddress,
+// looked up once per device (with that device current) and kept here.
+constexpr size_t kScratchBytes = PTFLASH_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_addr[kMaxDevices] = {};
+
+static int scratch_address(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return PTFLASH_EHIP;
+    if (dev < 0 || dev >= kMaxDevices) return PTFLASH_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *a = nullptr;
+        if (hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)) != hipSuccess || !a) return PTFLASH_EHIP;
+        g_scratch_addr[dev] = a;
+    }
+    *out = g_scratch_addr[dev];
+    return PTFLASH_OK;
+}
 
 static void fill_args(FlashArgs &a, const ptflash_problem *p, const ptflash_options *o,
                       const ptflash_result *r)
@@ -634,13 +660,27 @@ int ptflash_flash_ragged(const ptflash_ragged_problem *p, const ptflash_options 
     return PTFLASH_OK;
 }
 
+int ptflash_flash_noalloc(const ptflash_problem *p, const ptflash_options *o,
+                          ptflash_result *r, hipStream_t s)
+{
+    if (!problem_ok(p) || !options_ok(o) || !r) return PTFLASH_EINVAL;
+    if (p->nc < kMinNc || p->nc > kMaxNc) return PTFLASH_EUNSUPPORTED;
+    if (p->n == 0) return PTFLASH_OK;
+    if (ptflash_workspace_bytes(p, o) > kScratchBytes) return PTFLASH_EWORKSPACE;
+    void *ws = nullptr;
+    const int rc = scratch_address(&ws);
+    if (rc != PTFLASH_OK) return rc;
+    return ptflash_flash(p, o, r, ws, kScratchBytes, s);
+}
+
 const char *ptflash_strerror(int code)
 {
     switch (code) {
     case PTFLASH_OK: return "ok";
     case PTFLASH_EINVAL: return "invalid argument";
     case PTFLASH_EUNSUPPORTED: return "unsupported component count, layout or form";
-    case PTFLASH_EWORKSPACE: return "workspace too small";
+    case PTFLASH_EWORKSPACE:
+        return "workspace too small (ptflash_flash_noalloc: problem exceeds its scratch buffer)";
     case PTFLASH_EHIP: return "HIP runtime error";
     default: return "unknown error";
     }

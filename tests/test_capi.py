@@ -52,7 +52,7 @@ def test_rejects_malformed_calls_without_gpu():
     p0 = _capi.Problem(n=0, nc=3)
     assert L.ptflash_flash(C.byref(p0), C.byref(o), C.byref(r), None, 0, None) == 0
     assert L.ptflash_workspace_bytes(C.byref(p), C.byref(o)) >= 8
-    assert L.ptflash_strerror(3) == b"workspace too small"
+    assert L.ptflash_strerror(3).startswith(b"workspace too small")
     # one component set per mixture is accepted; other values are not
     pm = _capi.Problem(n=5, nc=3, props_per_mixture=2, z=8, T=8, P=8, Tc=8, Pc=8, omega=8,
                        kij=8)
@@ -127,3 +127,30 @@ def test_binding_checks_shapes_before_any_launch():
             api._check_ragged(2, 5, T2, nc_of, o2.to(torch.int64), k2.to(torch.int64), zz, zz,
                               zz, kij2)
     assert np.isfinite(w.z).all()
+
+
+def test_noalloc_rejects_problems_beyond_its_scratch_without_gpu():
+    # the size check of the allocation-free entry point comes before any HIP
+    # call: a problem whose workspace exceeds the library's scratch buffer is
+    # refused with PTFLASH_EWORKSPACE (the pointers are never dereferenced)
+    L = _capi.lib()
+    o = _capi.default_options()
+    r = _capi.Result(label=8, beta=8, x=8, y=8)
+    assert L.ptflash_flash_noalloc(None, C.byref(o), C.byref(r), None) == 1
+    fits = {}
+    for nc in (8, 20):
+        p = _capi.Problem(n=10_000_000, nc=nc, z=8, T=8, P=8, Tc=8, Pc=8, omega=8, kij=8)
+        assert L.ptflash_workspace_bytes(C.byref(p), C.byref(o)) > _capi.NOALLOC_SCRATCH_BYTES
+        assert L.ptflash_flash_noalloc(C.byref(p), C.byref(o), C.byref(r), None) == 3
+        # largest batch that fits (persistent form), for the limit the header states
+        lo, hi = 1, 10_000_000
+        while lo < hi:
+            mid = (lo + hi + 1) // 2
+            p.n = mid
+            if L.ptflash_workspace_bytes(C.byref(p), C.byref(o)) <= _capi.NOALLOC_SCRATCH_BYTES:
+                lo = mid
+            else:
+                hi = mid - 1
+        fits[nc] = lo
+    assert 90_000 < fits[8] < 120_000 and 40_000 < fits[20] < 55_000, fits
+    assert b"scratch" in L.ptflash_strerror(3)
