@@ -64,6 +64,10 @@ extern "C" {
 #define PTFLASH_ST_SWAPPED        0x0200u /* phases re-labelled so that Z_y > Z_x */
 #define PTFLASH_ST_STEP_CAP       0x0400u /* stopped by the per-mixture step cap */
 #define PTFLASH_ST_HINTED         0x0800u /* label set by the caller's hint */
+#define PTFLASH_ST_SPLIT_RESTART  0x1000u /* the split restarted from the composition
+                                             that proved the instability (substitution
+                                             left the two-phase region, or the first
+                                             descent ended at a degenerate split) */
 
 /* ---- iteration counters (iters[m*PTFLASH_NITERS + k]) ---- */
 #define PTFLASH_IT_PRE 0        /* initial phase-split substitutions (<= 3)  */

@@ -32,6 +32,7 @@ INFO_FIELDS = ["case", "pre", "ss_v", "nt_v", "ss_l", "nt_l", "ss_split",
 FLAG_INVALID, FLAG_SA_UNCONV, FLAG_SPLIT_UNCONV = 1, 2, 4
 FLAG_SPLIT_TRIVIAL, FLAG_SPLIT_FAILED, FLAG_RR_NO_ROOT = 8, 16, 32
 FLAG_HINTED = 64
+FLAG_SPLIT_RESTART = 128
 
 _D = C.POINTER(C.c_double)
 

@@ -62,6 +62,13 @@
  *   R9  canonical orientation of a two-phase result: y is the phase with
  *       the larger compressibility factor; single-phase results report
  *       x = y = z and beta = -1.
+ *   R21 a split whose substitution leaves the two-phase region (no
+ *       Rachford-Rice root, or theta outside (0,1)), or whose first descent
+ *       ends at a degenerate split, restarts once from n^V = beta w, w the
+ *       composition that proved the instability (the stability trial the K
+ *       re-estimate uses, or the triage's phase with the smaller tpd), beta
+ *       halved from min(1, min z_i/w_i)/2 until G is below the feed's.
+ *   R22 the K re-estimate never takes a trial whose tm is not a number.
  */
 #include <math.h>
 #include <stdint.h>
@@ -104,6 +111,7 @@ typedef struct {
 #define ORC_SPLIT_FAILED  16u
 #define ORC_RR_NO_ROOT    32u
 #define ORC_HINTED        64u
+#define ORC_SPLIT_RESTART 128u   /* split restarted from the unstable trial (R21) */
 
 /* info[] layout per mixture */
 enum {
@@ -726,6 +734,31 @@ static int orc_split_ss(const orc_eos *e, const double *z, double *lnK,
     return u;
 }
 
+/* R21: start of the phase split from a composition w with negative
+ * tangent-plane distance, when the substitution left the two-phase region:
+ * n^V = beta w with beta = min(1, min_i z_i / w_i) / 2, halved (at most 30
+ * times) until the split's G per unit feed is below the feed's, G_feed =
+ * sum z_i d_i, by more than 1e-12 (1 + |G_feed|).  For small beta,
+ * G - G_feed = beta tpd(w) + O(beta^2) < 0.  Returns 0 and n^V on success. */
+static int orc_split_restart(const orc_eos *e, const double *z, const double *d,
+                             const double *w, double *nV)
+{
+    int nc = e->nc;
+    double gf = 0.0, bmax = 1.0, r[ORC_NCMAX];
+    for (int i = 0; i < nc; ++i) {
+        gf += z[i] * d[i];
+        if (z[i] / w[i] < bmax) bmax = z[i] / w[i];
+    }
+    double beta = 0.5 * bmax;
+    for (int h = 0; h <= 30; ++h, beta *= 0.5) {
+        for (int i = 0; i < nc; ++i) nV[i] = beta * w[i];
+        double G;
+        orc_split_res(e, z, nV, r, &G);
+        if (G < gf - 1e-12 * (1.0 + fabs(gf))) return 0;
+    }
+    return 1;
+}
+
 /* G and its gradient over the vapour mole numbers (eqs. gibbs, split_grad). */
 typedef struct { const orc_eos *e; const double *z; } orc_split_ctx;
 
@@ -877,6 +910,15 @@ int orc_flash_one(int nc, const double *z_in, double T, double P,
         double dG = (1.0 - th) * tpdx + th * tpdy;               /* R2 */
         kase = (tpdx < -o->eps_tm || tpdy < -o->eps_tm || dG < -o->eps_tm) ? 3 : 2;
     }
+    /* R21: the composition with negative tangent-plane distance that proved
+     * the instability: the triage phase with the smaller tpd (case 3), or
+     * the stability trial the K re-estimate uses (below) */
+    double wst[ORC_NCMAX];
+    int have_w = 0;
+    if (kase == 3) {
+        for (int i = 0; i < nc; ++i) wst[i] = tpdx <= tpdy ? x[i] : y[i];
+        have_w = 1;
+    }
     res->info[ORC_I_CASE] = kase;
     res->info[ORC_I_PRE] = npre;
     /* the decisive value of a case-3 mixture: the most negative of the
@@ -906,11 +948,18 @@ int orc_flash_one(int nc, const double *z_in, double T, double P,
         /* the decisive value after stability analysis: the smaller final tm */
         res->tm_dec = fmin(tmt[0], tmt[1]);
         if (unstable) {
-            /* K re-estimate (Sec. 2.2.1, last paragraph) */
-            if (tmt[1] < tmt[0])
+            /* K re-estimate (Sec. 2.2.1, last paragraph) from the trial with
+             * the smaller tm; a trial whose substitution diverged (tm not a
+             * number) is never the one taken (R22) */
+            const int ts = (tmt[1] < tmt[0] || isnan(tmt[0])) ? 1 : 0;
+            if (ts == 1)
                 for (int i = 0; i < nc; ++i) lnK[i] = lnz[i] - lnWt[1][i];
             else
                 for (int i = 0; i < nc; ++i) lnK[i] = lnWt[0][i] - lnz[i];
+            double sw = 0.0;
+            for (int i = 0; i < nc; ++i) { wst[i] = exp(lnWt[ts][i]); sw += wst[i]; }
+            for (int i = 0; i < nc; ++i) wst[i] /= sw;
+            have_w = 1;
         }
     }
 
@@ -958,24 +1007,38 @@ int orc_flash_one(int nc, const double *z_in, double T, double P,
     int nss = orc_split_ss(&e, z, lnK, o, &conv, &rrf);
     res->info[ORC_I_SS_SPLIT] = nss;
     res->info[ORC_I_SPLIT_SS_CONV] = conv;
-    double thf;
+    double thf, nV[ORC_NCMAX];
     for (int i = 0; i < nc; ++i) K[i] = exp(lnK[i]);
-    if (rrf || orc_rr_solve(nc, z, K, &thf) != 0) {
-        res->info[ORC_I_FLAGS] = (int32_t)(flags | ORC_RR_NO_ROOT | ORC_SPLIT_FAILED);
-        return 0;
+    const int no_root = rrf || orc_rr_solve(nc, z, K, &thf) != 0;
+    if (no_root || !(thf > 0.0 && thf < 1.0)) {
+        /* R21: the substitution left the two-phase region; restart from the
+         * composition that proved the instability */
+        if (!have_w || orc_split_restart(&e, z, d, wst, nV) != 0) {
+            res->info[ORC_I_FLAGS] =
+                (int32_t)(flags | (no_root ? ORC_RR_NO_ROOT : 0u) | ORC_SPLIT_FAILED);
+            return 0;
+        }
+        flags |= ORC_SPLIT_RESTART;
+    } else {
+        orc_xy_from_k(nc, z, K, thf, x, y);
+        for (int i = 0; i < nc; ++i) nV[i] = thf * y[i];
     }
-    if (!(thf > 0.0 && thf < 1.0)) {
-        res->info[ORC_I_FLAGS] = (int32_t)(flags | ORC_SPLIT_FAILED);
-        return 0;
-    }
-    double nV[ORC_NCMAX];
-    orc_xy_from_k(nc, z, K, thf, x, y);
-    for (int i = 0; i < nc; ++i) nV[i] = thf * y[i];
     int nnt = 0;
     if (orc_split_newton(&e, z, nV, o, &nnt) != 0) flags |= ORC_SPLIT_UNCONV;
-    res->info[ORC_I_NT_SPLIT] = nnt;
     double bv = 0.0;
     for (int i = 0; i < nc; ++i) bv += nV[i];
+    if (!(bv > 1e-10 && bv < 1.0 - 1e-10) && !(flags & ORC_SPLIT_RESTART) && have_w &&
+        orc_split_restart(&e, z, d, wst, nV) == 0) {
+        /* R21: the descent ended at a degenerate split; restart once from
+         * the composition that proved the instability */
+        flags = (flags & ~ORC_SPLIT_UNCONV) | ORC_SPLIT_RESTART;
+        int n2 = 0;
+        if (orc_split_newton(&e, z, nV, o, &n2) != 0) flags |= ORC_SPLIT_UNCONV;
+        nnt += n2;
+        bv = 0.0;
+        for (int i = 0; i < nc; ++i) bv += nV[i];
+    }
+    res->info[ORC_I_NT_SPLIT] = nnt;
     /* a phase holding less than 1e-10 of the feed: degenerate split */
     if (!(bv > 1e-10 && bv < 1.0 - 1e-10)) {
         res->info[ORC_I_FLAGS] = (int32_t)(flags | ORC_SPLIT_FAILED);

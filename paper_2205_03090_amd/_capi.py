@@ -16,7 +16,7 @@ FORM_PERSISTENT, FORM_PLAIN = 0, 1
 ST = dict(INVALID=0x0001, SHORTCUT=0x0002, SA_RAN=0x0004, SA_UNCONV=0x0008,
           SPLIT_TR=0x0010, SPLIT_UNCONV=0x0020, SPLIT_TRIVIAL=0x0040,
           SPLIT_FAILED=0x0080, RR_NO_ROOT=0x0100, SWAPPED=0x0200, STEP_CAP=0x0400,
-          HINTED=0x0800)
+          HINTED=0x0800, SPLIT_RESTART=0x1000)
 EXPORTS = ["ptflash_default_options", "ptflash_max_nc", "ptflash_workspace_bytes",
            "ptflash_flash", "ptflash_flash_backward", "ptflash_backward_workspace_bytes",
            "ptflash_eval_phase", "ptflash_strerror", "ptflash_ragged_workspace_bytes",

@@ -25,13 +25,15 @@ namespace ptf {
 // Component counts from which the group variants are compiled.
 constexpr int kGroupMinNc = 8;
 
-// LDS doubles of one group: the factor (nc + 1 rows of nc: row i of L, and
-// a spare row that the lanes beyond nc write to) and five broadcast vectors
-// of G entries.
+// LDS doubles of one group: the factor (nc + 1 rows of LD doubles: row i of
+// L, and a spare row that the lanes beyond nc write to) and five broadcast
+// vectors of G entries.  The row stride LD = nc + 1 is odd, so that the lanes
+// of a group, each reading its own row, fall in different banks.
 template <int NC, int G>
 struct GroupLds {
+    static constexpr int LD = NC + 1;
     static constexpr int L = 0;
-    static constexpr int V = (NC + 1) * NC;
+    static constexpr int V = (NC + 1) * LD;
     static constexpr int N = V + 5 * G;
 };
 
@@ -87,8 +89,27 @@ struct Grp {
     int base;     // first lane of the group in the wavefront
     bool act;     // gi < NC
     double *sh;   // GroupLds<NC, G>::N doubles
+    const double *ks;   // the block's kappa table in LDS (shared component set only)
+    static constexpr int LD = GroupLds<NC, G>::LD;   // factor row stride
     __device__ __forceinline__ double *vec(int q) const { return sh + GroupLds<NC, G>::V + q * G; }
     __device__ __forceinline__ double *lsh() const { return sh + GroupLds<NC, G>::L; }
+};
+
+// Row gi of the table kappa_ij = 1 - k_ij of the caller's mixture: for a
+// shared component set a view of the block's table in LDS (loaded once per
+// block), for one set per mixture the row in registers.
+struct KapLds {
+    // odd row stride: the lanes of a group, each on its own row, read
+    // different banks
+    template <int NC>
+    static constexpr int stride() { return NC + 1; }
+    const double *row;
+    __device__ __forceinline__ double operator[](int j) const { return row[j]; }
+};
+template <int NC>
+struct KapRegs {
+    double v[NC];
+    __device__ __forceinline__ double operator[](int j) const { return v[j]; }
 };
 
 // Phase evaluation E(c) of one mixture across its group: this lane's share is
@@ -99,10 +120,9 @@ struct PhaseG {
     double psi, lnphi;   // this lane's component
 };
 
-template <int NC, int G>
+template <int NC, int G, class Kap>
 __device__ __forceinline__ void phase_eval_g(PhaseG &o, const Grp<NC, G> &g, double s, double b,
-                                             const double (&kap)[NC], double w, uint32_t &fl,
-                                             double zs)
+                                             const Kap &kap, double w, uint32_t &fl, double zs)
 {
     const double sum = gsum<G>(w);
     const double inv = 1.0 / sum;
@@ -133,10 +153,10 @@ __device__ __forceinline__ void phase_eval_g(PhaseG &o, const Grp<NC, G> &g, dou
 // phase_derivs) to hrow[j] for every j, and the diagonal term to hdiag (the
 // same bits as hrow[gi]); v is this lane's entry of the scaling vector (0 on
 // inactive lanes, where wrow is 0 too).
-template <int NC, int G>
+template <int NC, int G, class Kap>
 __device__ __forceinline__ void phase_derivs_g(double (&hrow)[NC], double &hdiag, const PhaseG &o,
                                                const Grp<NC, G> &g, double s, double b,
-                                               const double (&kap)[NC], double wrow, double v,
+                                               const Kap &kap, double wrow, double v,
                                                uint32_t &fl)
 {
     const double A = o.A, B = o.B, Z = o.Z, L = o.L;
@@ -177,49 +197,50 @@ __device__ __forceinline__ void phase_derivs_g(double (&hrow)[NC], double &hdiag
 }
 
 // Cholesky factor of H + shift I, H = M + diag(dadd) with M given by rows
-// (hrow) and dadd this lane's diagonal addend: row gi of L in lrow (entries
-// past the diagonal are not meaningful), the whole factor in the group's LDS
-// (lower triangle and diagonal), 1/L_ii of this row in dinv.  Returns
-// whether every pivot was positive (the same in every lane).  As cholesky.
+// (hrow) and dadd this lane's diagonal addend: the factor in the group's LDS,
+// row gi by this lane (entries past the diagonal are not meaningful; the
+// diagonal is written by lane j at step j), 1/L_ii of this row in dinv.
+// Returns whether every pivot was positive (the same in every lane).  As
+// cholesky.
 template <int NC, int G>
-__device__ __forceinline__ bool chol_g(double (&lrow)[NC], double &dinv,
-                                       const double (&hrow)[NC], double dadd, double shift,
-                                       const Grp<NC, G> &g, uint32_t &fl)
+__device__ __forceinline__ bool chol_g(double &dinv, const double (&hrow)[NC], double dadd,
+                                       double shift, const Grp<NC, G> &g, uint32_t &fl)
 {
+    constexpr int LD = Grp<NC, G>::LD;
     double *Ls = g.lsh();
+    double *mine = Ls + g.row * LD;
     bool ok = true;
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
         double s = hrow[j];
 #pragma unroll
-        for (int k = 0; k < j; ++k) s -= lrow[k] * Ls[j * NC + k];
+        for (int k = 0; k < j; ++k) s -= mine[k] * Ls[j * LD + k];
         // lane j's s is the pivot (before its diagonal terms)
         const double piv = gbcast(s + dadd, g.base, j) + shift;
         ok = ok && (piv > 0.0);
         const double d = sqrt(fmax(piv, 1e-300));
         const double dj = 1.0 / d;
-        lrow[j] = s * dj;
-        Ls[g.row * NC + j] = lrow[j];
-        Ls[j * NC + j] = d;
+        mine[j] = s * dj;
+        Ls[j * LD + j] = d;
         wave_lds_sync();
     }
-    dinv = 1.0 / Ls[g.row * NC + (g.act ? g.gi : 0)];
+    dinv = 1.0 / mine[g.act ? g.gi : 0];
     fl += Cost<NC>::chol;
     return ok;
 }
 
 // y = L^-1 b (forward substitution; this lane's entries of b and y).
 template <int NC, int G>
-__device__ __forceinline__ double lower_solve_g(const double (&lrow)[NC], double dinv, double b,
-                                                const Grp<NC, G> &g)
+__device__ __forceinline__ double lower_solve_g(double dinv, double b, const Grp<NC, G> &g)
 {
+    const double *mine = g.lsh() + g.row * Grp<NC, G>::LD;
     double *yv = g.vec(1);
     double r = b;
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
         const double yj = gbcast(r * dinv, g.base, j);
         yv[j] = yj;
-        r -= lrow[j] * yj;   // used by the lanes past j only
+        r -= mine[j] * yj;   // used by the lanes past j only
     }
     wave_lds_sync();
     const double y = yv[g.act ? g.gi : 0];
@@ -239,7 +260,7 @@ __device__ __forceinline__ double upper_solve_g(double dinv, double y, const Grp
     for (int k = NC - 1; k >= 0; --k) {
         const double xk = gbcast(r * dinv, g.base, k);
         xv[k] = xk;
-        r -= Ls[k * NC + col] * xk;   // used by the lanes before k only
+        r -= Ls[k * Grp<NC, G>::LD + col] * xk;   // used by the lanes before k only
     }
     wave_lds_sync();
     const double x = xv[col];
@@ -264,22 +285,22 @@ __device__ __forceinline__ double hv_g(const double (&hrow)[NC], double dadd, do
 
 // Trust-region step of Hebden type across the group: as trust_step, with
 // this lane's entries of u and g, row of M and diagonal term (H = M +
-// diag(dadd), M_ii = hdiag); lrow/dinv hold this lane's row of the last
-// factor, the LDS the whole factor.  newton_only as in trust_step.
+// diag(dadd), M_ii = hdiag); the group's LDS holds the last factor, dinv
+// this lane's 1/L_ii.  newton_only as in trust_step.
 template <int NC, int G>
 __device__ __forceinline__ double trust_step_g(double &u, double &radius, bool &eta0,
-                                               double (&lrow)[NC], double &dinv,
-                                               const double (&hrow)[NC], double hdiag,
-                                               double dadd, double gv, const Grp<NC, G> &g,
-                                               uint32_t &fl, bool newton_only = false)
+                                               double &dinv, const double (&hrow)[NC],
+                                               double hdiag, double dadd, double gv,
+                                               const Grp<NC, G> &g, uint32_t &fl,
+                                               bool newton_only = false)
 {
     const double mg = -gv;
     eta0 = false;
     bool have = false;
     double eta1 = -1.0;
     u = 0.0;
-    if (chol_g<NC, G>(lrow, dinv, hrow, dadd, 0.0, g, fl)) {
-        const double y = lower_solve_g<NC, G>(lrow, dinv, mg, g);
+    if (chol_g<NC, G>(dinv, hrow, dadd, 0.0, g, fl)) {
+        const double y = lower_solve_g<NC, G>(dinv, mg, g);
         u = upper_solve_g<NC, G>(dinv, y, g);
         fl += Cost<NC>::trisolve;
         const double nu = sqrt(gsum<G>(u * u));
@@ -288,7 +309,7 @@ __device__ __forceinline__ double trust_step_g(double &u, double &radius, bool &
             eta0 = true;
             have = true;
         } else {
-            const double q = lower_solve_g<NC, G>(lrow, dinv, u, g);
+            const double q = lower_solve_g<NC, G>(dinv, u, g);
             const double nq = sqrt(gsum<G>(q * q));
             eta1 = (nu / nq) * (nu / nq) * (nu - radius) / radius;
             fl += NC * NC + 2 * NC + 6;
@@ -309,12 +330,12 @@ __device__ __forceinline__ double trust_step_g(double &u, double &radius, bool &
         double eta = elo > 0.0 ? elo : 1e-3 * ehi;
         if (eta1 > 0.0 && eta1 < ehi) eta = eta1;
         for (int it = 0; it < 12; ++it) {
-            if (!chol_g<NC, G>(lrow, dinv, hrow, dadd, eta, g, fl)) {
+            if (!chol_g<NC, G>(dinv, hrow, dadd, eta, g, fl)) {
                 elo = eta;
                 eta = fmax(sqrt(elo * ehi), elo + 1e-3 * (ehi - elo));
                 continue;
             }
-            const double y = lower_solve_g<NC, G>(lrow, dinv, mg, g);
+            const double y = lower_solve_g<NC, G>(dinv, mg, g);
             const double ut = upper_solve_g<NC, G>(dinv, y, g);
             fl += Cost<NC>::trisolve;
             const double nu = sqrt(gsum<G>(ut * ut));
@@ -322,7 +343,7 @@ __device__ __forceinline__ double trust_step_g(double &u, double &radius, bool &
             have = true;
             if (nu > 0.9 * radius && nu < 1.1 * radius) break;
             if (nu > radius) elo = eta; else ehi = eta;
-            const double q = lower_solve_g<NC, G>(lrow, dinv, ut, g);
+            const double q = lower_solve_g<NC, G>(dinv, ut, g);
             const double nq = sqrt(gsum<G>(q * q));
             double en = eta + (nu / nq) * (nu / nq) * (nu - radius) / radius;
             if (!(en > elo && en < ehi)) en = fmax(sqrt(elo * ehi), elo + 1e-3 * (ehi - elo));
@@ -345,16 +366,23 @@ __device__ __forceinline__ double trust_step_g(double &u, double &radius, bool &
     return gu + 0.5 * uhu;
 }
 
-// Row gi of the k table as kappa_ij = 1 - k_ij (kappa_ii = 1: a valid set has
-// a zero diagonal; the lanes beyond nc read row 0 and contribute nothing).
+// Row gi of the table kappa_ij = 1 - k_ij of mixture m (kappa_ii = 1: a
+// valid set has a zero diagonal; the lanes beyond nc read row 0 and
+// contribute nothing): the block's LDS table for a shared set, the
+// mixture's row in registers for one set per mixture.
 template <int NC, bool PM, int G>
-__device__ __forceinline__ void load_kappa(double (&kap)[NC], const Ctx<NC> &c, int64_t m,
-                                           const Grp<NC, G> &g)
+__device__ __forceinline__ auto kappa_of(const Ctx<NC> &c, int64_t m, const Grp<NC, G> &g)
 {
-    const Props pp = mix_props<NC, PM>(c.pr, m);
     const int row = g.act ? g.gi : 0;
+    if constexpr (PM) {
+        const Props pp = mix_props<NC, PM>(c.pr, m);
+        KapRegs<NC> k;
 #pragma unroll
-    for (int j = 0; j < NC; ++j) kap[j] = 1.0 - pp.K[row * NC + j];
+        for (int j = 0; j < NC; ++j) k.v[j] = 1.0 - pp.K[row * NC + j];
+        return k;
+    } else {
+        return KapLds{g.ks + row * KapLds::stride<NC>()};
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -411,8 +439,7 @@ struct SaTrGroup {
     __device__ __forceinline__ bool step(const Ctx<NC> &c, const Grp<NC, G> &g)
     {
         const FlashArgs &a = c.a;
-        double kap[NC];
-        load_kappa<NC, PM, G>(kap, c, m, g);
+        const auto kap = kappa_of<NC, PM, G>(c, m, g);
         const double W = g.act ? exp(lw) : 0.0;
         fl += NC;
         PhaseG o;
@@ -464,9 +491,9 @@ struct SaTrGroup {
         phase_derivs_g<NC, G>(hrow, hdiag, o, g, s, b, kap, rc, rc, fl);
         const double dadd = 1.0 + 0.5 * grad;
         fl += 2 * Tri<NC>::N + 4 * NC;
-        double lrow[NC], dinv = 0.0, u;
+        double dinv = 0.0, u;
         bool eta0;
-        double pr = trust_step_g<NC, G>(u, rad, eta0, lrow, dinv, hrow, hdiag, dadd, gv, g, fl);
+        double pr = trust_step_g<NC, G>(u, rad, eta0, dinv, hrow, hdiag, dadd, gv, g, fl);
         const double bi = 2.0 * sqrt(W);
         const double amax = gmin<G>((g.act && u < 0.0) ? fmin(1.0, 0.99 * bi / -u) : 1.0);
         slen = amax * sqrt(gsum<G>(g.act ? u * u : 0.0));
@@ -501,10 +528,36 @@ struct SpNtGroup {
     double z, v0, v1, s, b;   // this lane's component
     double srad, sfacc, spred, sgacc, sdprev, zx, zy;
     double slen;   // scaled length of the last trust-region step taken
+    double sb, gf; // restart: current vapour amount of the start search, feed G
     bool tronly;   // refinement found H indefinite: take a trust-region step first
     bool spend, spol;
-    int tr, pol, steps;
+    bool start;    // restart: searching the start point (v1 holds the composition)
+    bool restarted;
+    int tr, pol, steps, nhalf, rstk;
+    int tr0;       // trust-region steps before a restart (each descent has the cap)
     uint32_t fl, status;
+
+    // Restart of the split from the composition that proved the
+    // instability (as SpNtItem::set_start).
+    __device__ __forceinline__ void set_start(const MixRec<NC> &r, int rs, const Grp<NC, G> &g)
+    {
+        const double w = g.act ? exp(r.lw[r.wsel][g.gi]) : 0.0;
+        const double sw = gsum<G>(w);
+        v1 = w * (1.0 / sw);
+        const double bmax = fmin(1.0, gmin<G>(g.act ? z / v1 : 1.0));
+        gf = gsum<G>(g.act ? z * r.d[g.gi] : 0.0);
+        sb = 0.5 * bmax;
+        v0 = sb * v1;
+        fl += 6 * NC + 2;
+        start = restarted = true;
+        nhalf = 0;
+        rstk = rs;
+        tr0 = tr;
+        steps = 0;   // the restart happens once: the item stays bounded
+        srad = 0.0;
+        spend = spol = tronly = false;
+        zx = zy = -1.0;
+    }
 
     __device__ __forceinline__ bool begin(const Ctx<NC> &c, uint32_t id, const Grp<NC, G> &g)
     {
@@ -524,8 +577,10 @@ struct SpNtGroup {
         status = r.status;
         srad = 0.0;
         spend = spol = tronly = false;
-        tr = pol = steps = 0;
+        start = restarted = false;
+        tr = pol = steps = tr0 = 0;
         zx = zy = -1.0;
+        if (r.rst != 0) set_start(r, r.rst, g);
         return true;
     }
 
@@ -560,8 +615,9 @@ struct SpNtGroup {
         }
     }
 
-    // savef: the group's LDS holds the factor of H' at the solution
-    __device__ __forceinline__ void finish(const Ctx<NC> &c, const Grp<NC, G> &g, double zx_,
+    // savef: the group's LDS holds the factor of H' at the solution.  As
+    // SpNtItem::finish: false when the split restarts instead.
+    __device__ __forceinline__ bool finish(const Ctx<NC> &c, const Grp<NC, G> &g, double zx_,
                                            double zy_, bool savef, double vs)
     {
         const FlashArgs &a = c.a;
@@ -574,12 +630,17 @@ struct SpNtGroup {
         xy_from_nv(x, y, bv);
         const double lk = gmax<G>(g.act ? fabs(log(y / x)) : 0.0);
         if (!(bv > kMinPhase && bv < 1.0 - kMinPhase)) {
+            if (!restarted && r.wsel >= 0) {
+                set_start(r, 1, g);
+                status = (status & ~(kStSplitUnconv | kStStepCap)) | kStSplitTr | kStSplitRestart;
+                return false;
+            }
             write_single(c, g, status | kStSplitFailed, it);
-            return;
+            return true;
         }
         if (lk < 1e-6) {
             write_single(c, g, status | kStSplitTrivial, it);
-            return;
+            return true;
         }
         const bool swap = zx_ > zy_;
         if (swap) status |= kStSwapped;
@@ -591,7 +652,8 @@ struct SpNtGroup {
                 const int i = g.gi;
                 const double *Ls = g.lsh();
                 for (int j = 0; j <= i; ++j)
-                    a.factor[m * NP + i * (i + 1) / 2 + j] = savef ? Ls[i * NC + j] / vs : NAN;
+                    a.factor[m * NP + i * (i + 1) / 2 + j] =
+                        savef ? Ls[i * Grp<NC, G>::LD + j] / vs : NAN;
             }
         }
         if (g.gi == 0) {
@@ -604,22 +666,22 @@ struct SpNtGroup {
             if (a.status) a.status[m] = (uint16_t)status;
             if (a.flops) a.flops[m] = fl;
         }
+        return true;
     }
 
     __device__ __forceinline__ bool step(const Ctx<NC> &c, const Grp<NC, G> &g)
     {
         const FlashArgs &a = c.a;
-        double kap[NC];
-        load_kappa<NC, PM, G>(kap, c, m, g);
+        const auto kap = kappa_of<NC, PM, G>(c, m, g);
         double w0, w1, bvap;
         xy_from_nv(w0, w1, bvap);
         // scaled Hessian H' = (I - v v' + V((1-th) Phi^V + th Phi^L)V)/(th(1-th)),
         // v_i = sqrt(x_i y_i / z_i)
         const double vs = g.act ? sqrt(w0 * w1 / z) : 0.0;
         fl += 4 * NC;
-        double hrow[NC], lrow[NC], hdiag = 0.0, dinv = 0.0;
+        double hrow[NC], hdiag = 0.0, dinv = 0.0;
 #pragma unroll
-        for (int j = 0; j < NC; ++j) { hrow[j] = 0.0; lrow[j] = 0.0; }
+        for (int j = 0; j < NC; ++j) hrow[j] = 0.0;
         PhaseG o;
         phase_eval_g<NC, G>(o, g, s, b, kap, w0, fl, zx);
         zx = o.Z;
@@ -639,6 +701,27 @@ struct SpNtGroup {
         const double gmx = gmax<G>(fabs(gt));
         const double gs = vs * gt;
         fl += 11 * NC;
+        if (start) {
+            // restart: the first point whose G is below the feed's starts the
+            // trust region; otherwise halve the vapour amount
+            if (G_ < gf - 1e-12 * (1.0 + fabs(gf))) {
+                start = false;
+            } else {
+                if (++nhalf > 30 || ++steps >= kStepGuard) {
+                    int16_t it[8];
+                    load_it<NC>(it, c.rec[m]);
+                    it[6] = (int16_t)tr;
+                    it[7] = (int16_t)pol;
+                    write_single(c, g, (status & ~kStSplitRestart) | kStSplitFailed |
+                                           (rstk == 2 ? kStRrNoRoot : 0u), it);
+                    return true;
+                }
+                sb *= 0.5;
+                v0 = sb * v1;
+                fl += NC;
+                return false;
+            }
+        }
         const double sc = 1.0 / (th * (1.0 - th));
         {
             double *vv = g.vec(0);
@@ -669,8 +752,7 @@ struct SpNtGroup {
                 v0 = v1;
                 if (++steps < kStepGuard) return false;   // re-evaluate there
                 status |= kStSplitUnconv | kStStepCap;
-                finish(c, g, Z0, o.Z, false, vs);
-                return true;
+                return finish(c, g, Z0, o.Z, false, vs);
             }
             if (ratio <= 0.25) srad = 0.5 * fmin(srad, slen);
             else if (ratio >= 0.75) srad *= 2.0;
@@ -685,25 +767,23 @@ struct SpNtGroup {
         // trust region, which starts from the same point at the next step.
         const bool newton = spol;
         if (!newton) {
-            if (tr >= a.max_tr_split || ++steps >= kStepGuard) {
+            if (tr - tr0 >= a.max_tr_split || ++steps >= kStepGuard) {
                 status |= kStSplitUnconv;
-                finish(c, g, Z0, o.Z, false, vs);
-                return true;
+                return finish(c, g, Z0, o.Z, false, vs);
             }
             status |= kStSplitTr;
         }
         double u;
         bool eta0;
         double rad = newton ? 1e300 : srad;
-        double pr = trust_step_g<NC, G>(u, rad, eta0, lrow, dinv, hrow, hdiag, dadd, gs, g, fl,
+        double pr = trust_step_g<NC, G>(u, rad, eta0, dinv, hrow, hdiag, dadd, gs, g, fl,
                                         newton);
         if (newton && !eta0) {
             spol = false;
             tronly = true;
             if (++steps < kStepGuard) return false;
             status |= kStSplitUnconv;
-            finish(c, g, Z0, o.Z, false, vs);
-            return true;
+            return finish(c, g, Z0, o.Z, false, vs);
         }
         if (!newton) {
             srad = rad;
@@ -721,8 +801,7 @@ struct SpNtGroup {
             const bool conv = dmax < a.tol_polish || (dmax < 1e-10 && dmax >= 0.5 * sdprev);
             if (conv || pol >= a.max_polish || ++steps >= kStepGuard) {
                 if (!conv && !(dmax < 1e-10)) status |= kStSplitUnconv;
-                finish(c, g, Z0, o.Z, true, vs);
-                return true;
+                return finish(c, g, Z0, o.Z, true, vs);
             }
             sdprev = dmax;
             ++pol;

@@ -28,9 +28,10 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Zeroes n counters of a counter block (kCounterStride apart).
 __global__ void reset_counters(unsigned long long *q, int n)
 {
-    if ((int)threadIdx.x < n) q[threadIdx.x] = 0ull;
+    if ((int)threadIdx.x < n) q[(size_t)threadIdx.x * kCounterStride] = 0ull;
 }
 
 // Number of items of a stage: all mixtures for the first stage, else the
@@ -39,8 +40,8 @@ template <class Item, int NC>
 __device__ __forceinline__ int64_t stage_count(const Ctx<NC> &c)
 {
     if (Item::LIST < 0) return c.a.n;
-    int64_t k = (int64_t)c.L.count[Item::LIST];
-    if (Item::LIST2 >= 0) k += (int64_t)c.L.count[Item::LIST2 < 0 ? 0 : Item::LIST2];
+    int64_t k = (int64_t)*c.L.cnt(Item::LIST);
+    if (Item::LIST2 >= 0) k += (int64_t)*c.L.cnt(Item::LIST2 < 0 ? 0 : Item::LIST2);
     return k;
 }
 
@@ -52,7 +53,7 @@ __device__ __forceinline__ uint32_t stage_id(const Ctx<NC> &c, int64_t k)
     constexpr int l1 = Item::LIST < 0 ? 0 : Item::LIST;
     if (Item::LIST2 >= 0) {
         constexpr int l2 = Item::LIST2 < 0 ? 0 : Item::LIST2;
-        const int64_t n1 = (int64_t)c.L.count[l1];
+        const int64_t n1 = (int64_t)*c.L.cnt(l1);
         if (k >= n1) return c.L.ids[l2][k - n1];
     }
     return c.L.ids[l1][k];
@@ -146,7 +147,7 @@ __device__ __forceinline__ void flush_list(const Lists &L, int list, const uint3
                                            int fill, int lane)
 {
     unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(&L.count[list], (unsigned long long)fill);
+    if (lane == 0) base = atomicAdd(L.cnt(list), (unsigned long long)fill);
     base = bcast64(base, 0);
     for (int k = lane; k < fill; k += 64) L.ids[list][base + (unsigned long long)k] = buf[k];
 }
@@ -187,7 +188,7 @@ __device__ __forceinline__ void append_slot(const Lists &L, int list, int l, uin
     const int tot = __popcll(m1) + __popcll(m2);
     const int leader = __ffsll((unsigned long long)__ballot(1)) - 1;   // lowest active lane
     unsigned long long base = 0;
-    if (lane == leader) base = atomicAdd(&L.count[list], (unsigned long long)tot);
+    if (lane == leader) base = atomicAdd(L.cnt(list), (unsigned long long)tot);
     base = bcast64(base, leader);
     if (mine) {
         const unsigned long long b = lanes_below(lane);
@@ -269,7 +270,16 @@ stage_persistent_group(Ctx<NC> c, const double *__restrict__ Tc, const double *_
     static_assert(Item::OUT == 0u, "group items append to no list");
     static_assert(64 % G == 0 && G >= NC, "a group spans the components within one wavefront");
     __shared__ double group_lds[kBlock / G][GroupLds<NC, G>::N];
+    // a shared component set: the table kappa_ij = 1 - k_ij once per block,
+    // rows KapLds::stride<NC>() apart
+    constexpr int KS = KapLds::stride<NC>();
+    __shared__ double kap_lds[Item::kPerMixture ? 1 : NC * KS];
     c.pr = Props{Tc, Pc, om, K};
+    if constexpr (!Item::kPerMixture) {
+        for (int t = (int)threadIdx.x; t < NC * NC; t += (int)blockDim.x)
+            kap_lds[(t / NC) * KS + t % NC] = 1.0 - K[t];
+        __syncthreads();
+    }
     const int64_t count = stage_count<Item, NC>(c);
     const int lane = (int)__lane_id();
     Grp<NC, G> g;
@@ -278,6 +288,7 @@ stage_persistent_group(Ctx<NC> c, const double *__restrict__ Tc, const double *_
     g.act = g.gi < NC;
     g.row = g.act ? g.gi : NC;
     g.sh = group_lds[threadIdx.x / G];
+    g.ks = Item::kPerMixture ? nullptr : kap_lds;
     Claim cl(count, (unsigned long long)gridDim.x * (blockDim.x / 64),
              (unsigned long long)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64);
     Item it;
@@ -527,6 +538,7 @@ constexpr int kNumCounters = 16;   // L_COUNT list counts, kNumStages take count
 constexpr int kTake0 = L_COUNT;
 constexpr int kPlain0 = L_COUNT + kNumStages;
 static_assert(kPlain0 + 2 <= kNumCounters, "counter block too small");
+constexpr size_t kCounterBytes = (size_t)kNumCounters * kCounterStride * 8;
 
 template <int NC>
 size_t plain_state_bytes()
@@ -545,7 +557,7 @@ template <int NC>
 size_t workspace_bytes(int64_t n, int form)
 {
     const size_t un = (size_t)n;
-    size_t b = 256 + align256(un * sizeof(MixRec<NC>)) + 3 * align256(2 * un * 4) +
+    size_t b = kCounterBytes + align256(un * sizeof(MixRec<NC>)) + 3 * align256(2 * un * 4) +
                4 * align256(un * 4);
     if (form == PTFLASH_FORM_PLAIN)
         b += align256(2 * un * plain_state_bytes<NC>()) + 2 * align256(2 * un * 4);
@@ -569,7 +581,7 @@ void setup_ctx(Ctx<NC> &c, const FlashArgs &a, int64_t n, void *ws, char **tail)
     Carve cv{(char *)ws};
     c.a = a;
     c.pr = Props{nullptr, nullptr, nullptr, nullptr};
-    unsigned long long *cnt = cv.take<unsigned long long>(256);
+    unsigned long long *cnt = cv.take<unsigned long long>(kCounterBytes);
     c.rec = cv.take<MixRec<NC>>((size_t)n * sizeof(MixRec<NC>));
     c.L.ids[L_SA] = cv.take<uint32_t>(2 * (size_t)n * 4);
     c.L.ids[L_SATR] = cv.take<uint32_t>(2 * (size_t)n * 4);
@@ -602,7 +614,7 @@ int run_persistent_stage(const Ctx<NC> &c, const ptflash_problem *p,
     const int grid = grid_for((const void *)stage_persistent<Item, NC>, block, o->grid);
     if (grid <= 0) return PTFLASH_EHIP;
     hipLaunchKernelGGL((stage_persistent<Item, NC>), dim3(grid), dim3(block), 0, s, c, p->Tc,
-                       p->Pc, p->omega, p->kij, c.L.count + take_slot);
+                       p->Pc, p->omega, p->kij, c.L.cnt(take_slot));
     return hipGetLastError() == hipSuccess ? PTFLASH_OK : PTFLASH_EHIP;
 }
 
@@ -615,7 +627,7 @@ int run_persistent_stage_group(const Ctx<NC> &c, const ptflash_problem *p,
     const int grid = grid_for((const void *)stage_persistent_group<Item, NC, G>, block, o->grid);
     if (grid <= 0) return PTFLASH_EHIP;
     hipLaunchKernelGGL((stage_persistent_group<Item, NC, G>), dim3(grid), dim3(block), 0, s, c,
-                       p->Tc, p->Pc, p->omega, p->kij, c.L.count + take_slot);
+                       p->Tc, p->Pc, p->omega, p->kij, c.L.cnt(take_slot));
     return hipGetLastError() == hipSuccess ? PTFLASH_OK : PTFLASH_EHIP;
 }
 
@@ -709,13 +721,13 @@ int run_plain_stage(const Ctx<NC> &c, const ptflash_problem *p, char *tail, hipS
     Item *states = cv.take<Item>(2 * (size_t)n * plain_state_bytes<NC>());
     uint32_t *la = cv.take<uint32_t>(2 * (size_t)n * 4);
     uint32_t *lb = cv.take<uint32_t>(2 * (size_t)n * 4);
-    unsigned long long *na = c.L.count + kPlain0, *nb = c.L.count + kPlain0 + 1;
+    unsigned long long *na = c.L.cnt(kPlain0), *nb = c.L.cnt(kPlain0 + 1);
     int64_t count = n;
     int rc;
-    if (Item::LIST >= 0 && (rc = read_count(c.L.count + Item::LIST, count, s))) return rc;
+    if (Item::LIST >= 0 && (rc = read_count(c.L.cnt(Item::LIST), count, s))) return rc;
     if (Item::LIST2 >= 0) {
         int64_t c2 = 0;
-        if ((rc = read_count(c.L.count + (Item::LIST2 < 0 ? 0 : Item::LIST2), c2, s))) return rc;
+        if ((rc = read_count(c.L.cnt(Item::LIST2 < 0 ? 0 : Item::LIST2), c2, s))) return rc;
         count += c2;
     }
     if (count == 0) return PTFLASH_OK;

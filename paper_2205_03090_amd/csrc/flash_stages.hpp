@@ -37,7 +37,13 @@
 //   * the split trust region is scaled: u = D^(1/2) dn with
 //     D = diag(z/(x y)), the paper's shift matrix;
 //   * the converged split is refined by Newton steps until max |dn| is
-//     below tol_polish, and y is chosen as the phase with the larger Z.
+//     below tol_polish, and y is chosen as the phase with the larger Z;
+//   * a split whose substitution leaves the two-phase region, or whose
+//     first descent ends degenerate, restarts once from n^V = beta w, w the
+//     composition that proved the instability (the trial the K re-estimate
+//     uses, or the triage's phase with the smaller tpd), beta halved from
+//     min(1, min z_i/w_i)/2 until G is below the feed's;
+//   * the K re-estimate never takes a trial whose tm is not a number.
 #pragma once
 
 #include <lane_value.hpp>   // angle brackets: a host build of the items substitutes its own
@@ -52,7 +58,7 @@ constexpr uint32_t kStInvalid = 0x0001u, kStShortcut = 0x0002u, kStSaRan = 0x000
                    kStSaUnconv = 0x0008u, kStSplitTr = 0x0010u, kStSplitUnconv = 0x0020u,
                    kStSplitTrivial = 0x0040u, kStSplitFailed = 0x0080u,
                    kStRrNoRoot = 0x0100u, kStSwapped = 0x0200u, kStStepCap = 0x0400u,
-                   kStHinted = 0x0800u;
+                   kStHinted = 0x0800u, kStSplitRestart = 0x1000u;
 
 // A split whose smaller phase holds less than this fraction of the feed is
 // reported as failed (single phase).
@@ -78,6 +84,10 @@ struct MixRec {
     uint32_t tfl[2];       // flops of each trial
     uint32_t tst[2];       // status bits of each trial
     int16_t it[8];
+    int32_t wsel;          // lw[wsel] holds ln of the composition that proved the
+                           // instability (a trial, or the triage's phase); -1: none
+    int32_t rst;           // split restart requested: 1 after theta left (0,1),
+                           // 2 after a Rachford-Rice solve without root; 0: none
 };
 
 
@@ -89,9 +99,18 @@ enum ListId : int {
     L_SA = 0, L_SATR = 1, L_SAFIN = 2, L_SPLIT = 3, L_NT = 4, L_PRE = 5, L_NTP = 6, L_COUNT = 7
 };
 
+// Device counters (list lengths, claim counters) sit 256 bytes apart: the
+// atomics on them are performed where the line lives, and counters sharing
+// a line would serialise each other's atomics.
+constexpr int kCounterStride = 32;   // unsigned long longs
+
 struct Lists {
     uint32_t *ids[L_COUNT];
-    unsigned long long *count;   // L_COUNT counters
+    unsigned long long *count;   // counter block: counter k at count[k * kCounterStride]
+    __host__ __device__ __forceinline__ unsigned long long *cnt(int k) const
+    {
+        return count + (size_t)k * kCounterStride;
+    }
 };
 
 // Read-only shared component set (restrict pointers: compile-time indexed
@@ -301,6 +320,8 @@ __device__ __forceinline__ void route_mixture(MixRec<NC> &r, Outbox &ob, int64_t
 #pragma unroll
     for (int k = 0; k < 8; ++k) r.it[k] = 0;
     r.it[0] = (int16_t)npre;
+    r.wsel = -1;
+    r.rst = 0;
     if (to_split) {
         ob.put(L_SPLIT, (uint32_t)m);
     } else {
@@ -505,6 +526,10 @@ struct PreSsItem {
                 return true;
             }
             route_mixture<NC>(r, ob, m, true, kStShortcut, fl, npre, lk, 0.5);
+            // the phase that proved the instability, for a restart of the split
+#pragma unroll
+            for (int i = 0; i < NC; ++i) r.lw[0][i] = log(tx <= ty ? w0[i] : w1[i]);
+            r.wsel = 0;
         } else
             route_mixture<NC>(r, ob, m, false, kStSaRan, fl, npre, lk, theta);
         return true;
@@ -811,13 +836,17 @@ struct SaFinItem {
             write_outputs_single<NC>(c, m, z, status, fl, it);
             return true;
         }
-        if (t1 < t0) {
+        // the trial with the smaller tm; a trial whose substitution diverged
+        // (tm not a number) is never the one taken
+        const int ts = (t1 < t0 || isnan(t0)) ? 1 : 0;
+        if (ts == 1) {
 #pragma unroll
             for (int i = 0; i < NC; ++i) r.lk[i] = r.lnz[i] - r.lw[1][i];
         } else {
 #pragma unroll
             for (int i = 0; i < NC; ++i) r.lk[i] = r.lw[0][i] - r.lnz[i];
         }
+        r.wsel = ts;
         r.theta = 0.5;
         r.status = status;
         r.fl = fl + NC;
@@ -875,6 +904,25 @@ struct SpSsItem {
         write_outputs_single<NC>(c, m, z, status | bits, fl, it);
     }
 
+    // The substitution left the two-phase region (no Rachford-Rice root, or
+    // theta outside (0,1)): the split restarts in the trust-region stage from
+    // the composition that proved the instability, when there is one;
+    // otherwise the mixture is reported single phase (SPLIT_FAILED).
+    __device__ __forceinline__ void restart_or_fail(const Ctx<NC> &c, bool no_root,
+                                                    uint32_t fail_bits)
+    {
+        MixRec<NC> &r = c.rec[m];
+        if (r.wsel < 0) {
+            fail(c, kStSplitFailed | (no_root ? kStRrNoRoot : 0u) | fail_bits);
+            return;
+        }
+        r.rst = no_root ? 2 : 1;
+        r.it[5] = (int16_t)ss;
+        r.fl = fl;
+        r.status = status | kStSplitTr | kStSplitRestart;
+        ob.put(L_NT, (uint32_t)m);
+    }
+
     __device__ __forceinline__ bool step(const Ctx<NC> &c)
     {
         const Props pp = mix_props<NC, PM>(c.pr, m);
@@ -889,7 +937,7 @@ struct SpSsItem {
                 for (int i = 0; i < NC; ++i) lk[i] -= sext * prev[i];
                 if (++steps < kStepGuard) return false;
             }
-            fail(c, kStRrNoRoot | kStSplitFailed);
+            restart_or_fail(c, true, 0u);
             return true;
         }
         Phase<NC> o;
@@ -944,8 +992,12 @@ struct SpSsItem {
         }
         // hand over to the trust region: n^V = theta y from the final K
         MixRec<NC> &r = c.rec[m];
-        if (!xy_from_lnk<NC>(x, y, lk, z, theta, fl) || !(theta > 0.0 && theta < 1.0)) {
-            fail(c, kStSplitFailed | (conv ? 0u : kStSplitTr));
+        if (!xy_from_lnk<NC>(x, y, lk, z, theta, fl)) {
+            restart_or_fail(c, true, conv ? 0u : kStSplitTr);
+            return true;
+        }
+        if (!(theta > 0.0 && theta < 1.0)) {
+            restart_or_fail(c, false, conv ? 0u : kStSplitTr);
             return true;
         }
 #pragma unroll
@@ -976,10 +1028,48 @@ struct SpNtItem {
     Eos<NC> e;
     double srad, sfacc, spred, sgacc, sdprev, zx, zy;   // zx, zy: previous Z
     double slen;   // scaled length of the last trust-region step taken
+    double sb, gf; // restart: current vapour amount of the start search, feed G
     bool spend, spol;
     bool tronly;   // refinement found H indefinite: take a trust-region step first
-    int tr, pol, steps;
+    bool start;    // restart: searching the start point (v1 holds the composition)
+    bool restarted;
+    int tr, pol, steps, nhalf, rstk;
+    int tr0;       // trust-region steps before a restart (each descent has the cap)
     uint32_t fl, status;
+
+    // Restart of the split from the composition w that proved the
+    // instability (record field lw[wsel]): n^V = beta w with
+    // beta = min(1, min_i z_i / w_i) / 2, halved until G is below the
+    // feed's (in step).  rs: the record's restart code.
+    __device__ __forceinline__ void set_start(const MixRec<NC> &r, int rs)
+    {
+        double sw = 0.0, bmax = 1.0, g = 0.0;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            v1[i] = exp(r.lw[r.wsel][i]);
+            sw += v1[i];
+        }
+        const double isw = 1.0 / sw;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            v1[i] *= isw;
+            bmax = fmin(bmax, z[i] / v1[i]);
+            g += z[i] * r.d[i];
+        }
+        sb = 0.5 * bmax;
+#pragma unroll
+        for (int i = 0; i < NC; ++i) v0[i] = sb * v1[i];
+        gf = g;
+        fl += 6 * NC + 2;
+        start = restarted = true;
+        nhalf = 0;
+        rstk = rs;
+        tr0 = tr;
+        steps = 0;   // the restart happens once: the item stays bounded
+        srad = 0.0;
+        spend = spol = tronly = false;
+        zx = zy = -1.0;
+    }
 
     __device__ __forceinline__ bool begin(const Ctx<NC> &c, uint32_t id)
     {
@@ -996,8 +1086,10 @@ struct SpNtItem {
         status = r.status;
         srad = 0.0;
         spend = spol = tronly = false;
-        tr = pol = steps = 0;
+        start = restarted = false;
+        tr = pol = steps = tr0 = 0;
         zx = zy = -1.0;
+        if (r.rst != 0) set_start(r, r.rst);
         return true;
     }
 
@@ -1019,7 +1111,11 @@ struct SpNtItem {
         fl += 5 * NC + 2;
     }
 
-    __device__ __forceinline__ void finish(const Ctx<NC> &c, double zx, double zy,
+    // Writes the outputs and returns true, or, when the split ended
+    // degenerate (a phase below kMinPhase of the feed) and has not been
+    // restarted yet, restarts it from the composition that proved the
+    // instability and returns false.
+    __device__ __forceinline__ bool finish(const Ctx<NC> &c, double zx, double zy,
                                            const double (&Lf)[NP], bool savef,
                                            const double (&vs)[NC])
     {
@@ -1035,12 +1131,17 @@ struct SpNtItem {
 #pragma unroll
         for (int i = 0; i < NC; ++i) lk = fmax(lk, fabs(log(y[i] / x[i])));
         if (!(bv > kMinPhase && bv < 1.0 - kMinPhase)) {
+            if (!restarted && r.wsel >= 0) {
+                set_start(r, 1);
+                status = (status & ~(kStSplitUnconv | kStStepCap)) | kStSplitTr | kStSplitRestart;
+                return false;
+            }
             write_outputs_single<NC>(c, m, z, status | kStSplitFailed, fl, it);
-            return;
+            return true;
         }
         if (lk < 1e-6) {
             write_outputs_single<NC>(c, m, z, status | kStSplitTrivial, fl, it);
-            return;
+            return true;
         }
         const bool swap = zx > zy;
         if (swap) status |= kStSwapped;
@@ -1065,6 +1166,7 @@ struct SpNtItem {
         }
         if (a.status) a.status[m] = (uint16_t)status;
         if (a.flops) a.flops[m] = fl;
+        return true;
     }
 
     __device__ __forceinline__ bool step(const Ctx<NC> &c)
@@ -1109,6 +1211,29 @@ struct SpNtItem {
             gs[i] = vs[i] * gt[i];
         }
         fl += 11 * NC;
+        if (start) {
+            // restart: the first point whose G is below the feed's starts the
+            // trust region; otherwise halve the vapour amount
+            if (G < gf - 1e-12 * (1.0 + fabs(gf))) {
+                start = false;
+            } else {
+                if (++nhalf > 30 || ++steps >= kStepGuard) {
+                    int16_t it[8];
+                    load_it<NC>(it, c.rec[m]);
+                    it[6] = (int16_t)tr;
+                    it[7] = (int16_t)pol;
+                    write_outputs_single<NC>(
+                        c, m, z, (status & ~kStSplitRestart) | kStSplitFailed |
+                                     (rstk == 2 ? kStRrNoRoot : 0u), fl, it);
+                    return true;
+                }
+                sb *= 0.5;
+#pragma unroll
+                for (int i = 0; i < NC; ++i) v0[i] = sb * v1[i];
+                fl += NC;
+                return false;
+            }
+        }
         const double sc = 1.0 / (th * (1.0 - th));
 #pragma unroll
         for (int i = 0; i < NC; ++i)
@@ -1137,8 +1262,7 @@ struct SpNtItem {
                 for (int i = 0; i < NC; ++i) v0[i] = v1[i];
                 if (++steps < kStepGuard) return false;   // re-evaluate there
                 status |= kStSplitUnconv | kStStepCap;
-                finish(c, Z0, o.Z, F, false, vs);
-                return true;
+                return finish(c, Z0, o.Z, F, false, vs);
             }
             if (ratio <= 0.25) srad = 0.5 * fmin(srad, slen);
             else if (ratio >= 0.75) srad *= 2.0;
@@ -1154,10 +1278,9 @@ struct SpNtItem {
         // same point at the next step.
         const bool newton = spol;
         if (!newton) {
-            if (tr >= a.max_tr_split || ++steps >= kStepGuard) {
+            if (tr - tr0 >= a.max_tr_split || ++steps >= kStepGuard) {
                 status |= kStSplitUnconv;
-                finish(c, Z0, o.Z, F, false, vs);
-                return true;
+                return finish(c, Z0, o.Z, F, false, vs);
             }
             status |= kStSplitTr;
         }
@@ -1170,8 +1293,7 @@ struct SpNtItem {
             tronly = true;
             if (++steps < kStepGuard) return false;
             status |= kStSplitUnconv;
-            finish(c, Z0, o.Z, F, false, vs);
-            return true;
+            return finish(c, Z0, o.Z, F, false, vs);
         }
         if (!newton) {
             srad = rad;
@@ -1194,8 +1316,7 @@ struct SpNtItem {
             const bool conv = dmax < a.tol_polish || (dmax < 1e-10 && dmax >= 0.5 * sdprev);
             if (conv || pol >= a.max_polish || ++steps >= kStepGuard) {
                 if (!conv && !(dmax < 1e-10)) status |= kStSplitUnconv;
-                finish(c, Z0, o.Z, F, true, vs);
-                return true;
+                return finish(c, Z0, o.Z, F, true, vs);
             }
             sdprev = dmax;
             ++pol;

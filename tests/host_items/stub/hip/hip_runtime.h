@@ -13,6 +13,7 @@ using std::fabs;
 using std::fmax;
 using std::fmin;
 using std::isfinite;
+using std::isnan;
 using std::log;
 using std::log1p;
 using std::sqrt;

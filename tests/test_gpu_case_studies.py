@@ -74,7 +74,10 @@ def test_table5_stage_shares_gpu():
     split = pct(entered)
     split_ss = 100.0 - pct(split_tr[entered])
     tr3 = pct(it[split_tr, IT["tr_split"]] <= 3)
-    mx = {k: int(it[:, IT[k]].max()) for k in ("tr_v", "tr_l", "tr_split")}
+    # largest counts over the mixtures that took the paper's path (a split
+    # restarted from the stability trial, reading R21, counts both descents)
+    plain = (st & ST["SPLIT_RESTART"]) == 0
+    mx = {k: int(it[plain, IT[k]].max()) for k in ("tr_v", "tr_l", "tr_split")}
     print(f"[cs9 table 5] shortcut {shortcut:.2f} % (paper {t5['initial_ss'][1]}); "
           f"stability runs {int(sa.sum())} (paper {t5['sa_ss_vapour'][0]}), substitution "
           f"V {ss_v:.2f} % L {ss_l:.2f} % (paper {t5['sa_ss_vapour'][1]} / "

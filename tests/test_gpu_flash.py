@@ -239,3 +239,31 @@ def test_eval_phase_dense_liquid_roots_along_split_paths():
         ref, info = oracle.lnphi(w.Tc, w.Pc, w.omega, w.kij, T[i], P[i], c[i])
         assert abs(Z[i] - info["Z"]) <= 1e-13 * info["Z"], (i, Z[i], info["Z"])
         assert np.abs(lp[i] - ref).max() < 1e-11, i
+
+
+def test_split_restart_matches_oracle():
+    # R21/R22: splits whose substitution leaves the two-phase region, or
+    # whose first descent ends degenerate, restart from the composition that
+    # proved the instability; both sides apply the rule, and no mixture proven
+    # unstable is reported single phase
+    w = workloads.nc8_workload(n=300_000)
+    print(f"case split restart n={w.n}", flush=True)
+    g = _run(w)
+    o = oracle.flash(w, threads=8, want_min_tpd=1)
+    flags = o["info"][:, oracle.INFO_FIELDS.index("flags")]
+    rst = np.where(flags & oracle.FLAG_SPLIT_RESTART)[0]
+    st = g["status"].astype(np.int64) & 0xFFFF
+    grst = np.where(st & _capi.ST["SPLIT_RESTART"])[0]
+    print(f"[restart] oracle {len(rst)} gpu {len(grst)}", flush=True)
+    assert len(rst) >= 3 and len(grst) >= 3
+    # the oracle's restarted splits and the GPU's, with a sample of the rest
+    rng = np.random.Generator(np.random.PCG64(19))
+    idx = np.unique(np.concatenate([rst, grst, rng.choice(w.n, 2000, replace=False)]))
+    sub = {k: (v[idx] if k != "info" else v[idx]) for k, v in o.items()}
+    rep = compare(g, sub, idx, w=w)
+    _report("restart", rep)
+    assert_parity(rep, sub, path_agree=0.97, min_two_phase_frac=0.1)
+    # no proven instability ends single phase on the GPU: a negative
+    # decisive tm with a failed split
+    tm = g["tm"]
+    assert not np.any((tm < -1e-10) & ((st & _capi.ST["SPLIT_FAILED"]) != 0))

@@ -269,3 +269,30 @@ def test_parity_gibbs_of_a_split_matches_the_oracle_residual_routine(orc, nc8):
         _, G = orc.split_residual(w.Tc, w.Pc, w.omega, w.kij, w.T[m], w.P[m], z,
                                   r["beta"][m] * r["y"][m])
         assert abs(split_gibbs(w, m, r["x"][m], r["y"][m], r["beta"][m]) - G) < 1e-12 * max(1, abs(G))
+
+
+def test_every_proven_instability_ends_in_a_valid_split(orc):
+    # R21/R22 on 200,000 mixtures of the Nc = 8 workload: every mixture that
+    # the triage or the stability analysis proves unstable ends two-phase
+    # (none SPLIT_FAILED), including those whose substitution left the
+    # two-phase region or whose vapour-like trial diverged; the restarted
+    # splits are checked like any other: material balance, equal fugacity
+    # evaluated afresh by the phase model, G below the feed's, and 0 < beta < 1
+    w = workloads.nc8_workload(n=200_000)
+    r = orc.flash(w, threads=8)
+    info = r["info"]
+    f = {k: i for i, k in enumerate(orc.INFO_FIELDS)}
+    unstable = info[:, f["unstable"]] == 1
+    flags = info[:, f["flags"]]
+    assert not np.any(unstable & ((flags & orc.FLAG_SPLIT_FAILED) != 0))
+    rst = np.where(flags & orc.FLAG_SPLIT_RESTART)[0]
+    assert len(rst) >= 3, len(rst)   # the restart is exercised
+    for m in rst:
+        x, y, b = r["x"][m], r["y"][m], r["beta"][m]
+        z = w.z[m] / w.z[m].sum()
+        assert r["label"][m] == 1 and 0 < b < 1
+        assert np.abs((1 - b) * x + b * y - z).max() < 1e-13
+        res, G = orc.split_residual(w.Tc, w.Pc, w.omega, w.kij, w.T[m], w.P[m], z, b * y)
+        assert np.all(np.abs(res) <= 1e-10), (m, res)
+        lpz, _ = orc.lnphi(w.Tc, w.Pc, w.omega, w.kij, w.T[m], w.P[m], z)
+        assert G < np.dot(z, np.log(z) + lpz)
