@@ -278,10 +278,16 @@ def main():
         # the second roofline view: FP64 VALU flops the hardware issued per
         # launch (rocprofv3 FP64 instruction counters, 64 lanes per wave
         # instruction, FMA = 2; transcendental and division sequences
-        # included) over this run's launch time
+        # included) over this run's launch time; lane_weighted counts only
+        # the lanes the exec mask enabled (each stage's issued flops times
+        # its SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU))
         "fp64_issued": ({"tflops": cnt["fp64_issued_flops_per_launch"] / (avg_ms * 1e-3) / 1e12,
                          "frac": cnt["fp64_issued_flops_per_launch"] / (avg_ms * 1e-3)
-                         / FP64_VECTOR_PEAK}
+                         / FP64_VECTOR_PEAK,
+                         "lane_weighted_frac": (cnt["fp64_lane_weighted_flops_per_launch"]
+                                                / (avg_ms * 1e-3) / FP64_VECTOR_PEAK
+                                                if "fp64_lane_weighted_flops_per_launch" in cnt
+                                                else None)}
                         if "fp64_issued_flops_per_launch" in cnt else None),
         # mean and max iteration counts per slot over the mixtures that ran it
         "iters": {nm: [float(g["iters"][:, k][g["iters"][:, k] > 0].mean())

@@ -81,8 +81,13 @@ extern "C" {
 #define PTFLASH_NITERS 8
 
 /* ---- execution forms ---- */
-#define PTFLASH_FORM_PERSISTENT 0 /* one launch; waves refill finished lanes  */
+#define PTFLASH_FORM_PERSISTENT 0 /* one launch per stage; waves refill finished
+                                     lanes.  A batch of n mixtures with
+                                     n * nc <= 600000 and grid, block and the
+                                     lanes options all 0 runs as FUSED     */
 #define PTFLASH_FORM_PLAIN 1      /* one launch per stage iteration + compaction */
+#define PTFLASH_FORM_FUSED 2      /* one launch; each lane carries one mixture
+                                     through every stage (small batches) */
 
 /* Problem description.  Every mixture has the same nc (2 <= nc <= the value
  * of ptflash_max_nc()).  props_per_mixture = 0: Tc, Pc, omega hold nc values
@@ -147,6 +152,9 @@ typedef struct {
     int32_t lanes_split;   /* the same choice for the split trust-region stage
                               alone: 0 = the tuned choice when
                               lanes_per_mixture is 0, else lanes_per_mixture */
+    int32_t lanes_ss;      /* the same choice for the two substitution stages
+                              (stability trials and split) of the persistent
+                              form: 0 = the tuned choice, 1, 16 or 32 */
 } ptflash_options;
 
 /* Outputs (device pointers).  label, beta, x, y are required; the others may

@@ -12,7 +12,7 @@ from . import build as _build
 
 NITERS = 8
 IT_NAMES = ["pre", "ss_v", "tr_v", "ss_l", "tr_l", "ss_split", "tr_split", "polish"]
-FORM_PERSISTENT, FORM_PLAIN = 0, 1
+FORM_PERSISTENT, FORM_PLAIN, FORM_FUSED = 0, 1, 2
 ST = dict(INVALID=0x0001, SHORTCUT=0x0002, SA_RAN=0x0004, SA_UNCONV=0x0008,
           SPLIT_TR=0x0010, SPLIT_UNCONV=0x0020, SPLIT_TRIVIAL=0x0040,
           SPLIT_FAILED=0x0080, RR_NO_ROOT=0x0100, SWAPPED=0x0200, STEP_CAP=0x0400,
@@ -46,7 +46,8 @@ class Options(C.Structure):
                 ("tol_split_tr", C.c_double), ("tol_polish", C.c_double),
                 ("eps_tm", C.c_double), ("form", C.c_int32), ("keep_factor", C.c_int32),
                 ("block", C.c_int32), ("grid", C.c_int32),
-                ("lanes_per_mixture", C.c_int32), ("lanes_split", C.c_int32)]
+                ("lanes_per_mixture", C.c_int32), ("lanes_split", C.c_int32),
+                ("lanes_ss", C.c_int32)]
 
 
 class Result(C.Structure):

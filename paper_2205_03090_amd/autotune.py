@@ -1,12 +1,16 @@
 """Chooses, per component count and layout of the component sets, the launch
 shape of the persistent flash on this GPU: the lanes per mixture of each of
-the two trust-region stages (1, or a group of 16 or 32 lanes) and the threads
-per block, by timing every candidate on seeded sample workloads.
+the two trust-region stages and of the two substitution stages (1, or a group
+of 16 or 32 lanes) and the threads per block, by timing candidates on seeded
+sample workloads: every pair of trust-region choices first (substitution
+lanes and block as they stand), then the substitution choice, then the
+block, each step keeping the best so far.
 
   python -m paper_2205_03090_amd.autotune --out DIR [--n 4000000] [--n-pm 1000000]
 
 writes DIR/tuned_gfx950.hpp (the table the library compiles in as its
-default, csrc/tuned_gfx950.hpp) and DIR/autotune_gfx950.md (the timings).
+default, csrc/tuned_gfx950.hpp; component counts outside --nc keep the
+current entries) and DIR/autotune_gfx950.md (the timings).
 The sample for nc is uniform_workload(seed 30000 + nc, alpha 0.5,
 T in [200, 600] K, P in [1e5, 2e7] Pa) with one shared component set, and
 per_mixture_workload_vec(seed 31000 + nc, same distributions) with one set
@@ -35,16 +39,10 @@ def lane_choices(nc: int):
     return lanes
 
 
-def candidates(nc: int):
-    """(stability lanes, split lanes, block) triples."""
-    ls = lane_choices(nc)
-    return [(a, b, k) for a in ls for b in ls for k in BLOCKS]
-
-
-def time_one(args, la: int, lb: int, block: int, reps: int) -> float:
+def time_one(args, la: int, lb: int, ls: int, block: int, reps: int) -> float:
     import torch
     from . import api
-    kw = dict(lanes_per_mixture=la, lanes_split=lb, block=block)
+    kw = dict(lanes_per_mixture=la, lanes_split=lb, lanes_ss=ls, block=block)
     out = api.flash(*args, **kw)
     api.flash(*args, out=out, **kw)
     ts = []
@@ -57,17 +55,34 @@ def time_one(args, la: int, lb: int, block: int, reps: int) -> float:
     return float(np.median(ts))
 
 
-def header(lanes_sa, lanes_sp, blocks) -> str:
+def current_table():
+    """The table compiled into the library (csrc/tuned_gfx950.hpp):
+    (lanes_sa, lanes_sp, blocks), each [layout][nc]."""
+    import re
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "tuned_gfx950.hpp")
+    with open(path) as f:
+        text = f.read()
+
+    def table(name):
+        body = re.search(name + r"\[2\]\[21\] = \{(.*?)\};", text, re.S).group(1)
+        rows = re.findall(r"\{([^{}]*)\}", body)
+        return [[int(v) for v in r.split(",")] for r in rows]
+
+    ss = table("kTunedLanesSs") if "kTunedLanesSs" in text else [[1] * 21, [1] * 21]
+    return table("kTunedLanesSa"), table("kTunedLanesSp"), ss, table("kTunedBlock")
+
+
+def header(lanes_sa, lanes_sp, lanes_ss, blocks) -> str:
     """lanes_sa etc.: [layout][nc], layout 0 = shared set, 1 = one per mixture."""
     def row(v):
         return "{" + ", ".join(str(x) for x in v) + "}"
     return f"""// tuned_gfx950.hpp -- launch shape of the persistent flash per component
 // count on gfx950: lanes per mixture of the stability and of the split
-// trust-region stage (1: one mixture per lane; 16 or 32: one group of that
-// many lanes per mixture) and threads per block, for a shared component set
-// (row 0) and for one set per mixture (row 1).  Written by autotune.py from
-// timed runs (the timings are in the autotune summary next to the
-// profiles).
+// trust-region stage and of the two substitution stages (1: one mixture per
+// lane; 16 or 32: one group of that many lanes per mixture) and threads per
+// block, for a shared component set (row 0) and for one set per mixture
+// (row 1).  Written by autotune.py from timed runs (the timings are in the
+// autotune summary next to the profiles).
 #pragma once
 
 namespace ptf {{
@@ -76,6 +91,8 @@ constexpr int kTunedLanesSa[2][21] = {{{row(lanes_sa[0])},
                                        {row(lanes_sa[1])}}};
 constexpr int kTunedLanesSp[2][21] = {{{row(lanes_sp[0])},
                                        {row(lanes_sp[1])}}};
+constexpr int kTunedLanesSs[2][21] = {{{row(lanes_ss[0])},
+                                       {row(lanes_ss[1])}}};
 constexpr int kTunedBlock[2][21] = {{{row(blocks[0])},
                                      {row(blocks[1])}}};
 
@@ -87,6 +104,11 @@ constexpr int tuned_lanes_sa(int nc, bool pm)
 constexpr int tuned_lanes_sp(int nc, bool pm)
 {{
     return (nc >= 0 && nc <= 20) ? kTunedLanesSp[pm ? 1 : 0][nc] : 1;
+}}
+
+constexpr int tuned_lanes_ss(int nc, bool pm)
+{{
+    return (nc >= 0 && nc <= 20) ? kTunedLanesSs[pm ? 1 : 0][nc] : 1;
 }}
 
 constexpr int tuned_block(int nc, bool pm)
@@ -109,9 +131,8 @@ def main():
     import torch
     lo, hi = (int(x) for x in a.nc.split("-"))
     dev = torch.device("cuda", 0)
-    lanes_sa = [[1] * 21, [1] * 21]
-    lanes_sp = [[1] * 21, [1] * 21]
-    blocks = [[256] * 21, [256] * 21]
+    # component counts outside --nc keep the library's current choice
+    lanes_sa, lanes_sp, lanes_ss, blocks = current_table()
     lines = ["# Launch-shape autotune (gfx950)", "",
              f"Command: `python -m paper_2205_03090_amd.autotune --out <dir> --n {a.n} "
              f"--n-pm {a.n_pm} --reps {a.reps} --nc {a.nc}`", "",
@@ -120,8 +141,9 @@ def main():
              f"{a.n_pm} mixtures of per_mixture_workload_vec(seed 31000 + nc, the same "
              f"distributions, one set per mixture); median of {a.reps} timed flashes "
              "after two untimed ones.", "",
-             "| sets | nc | lanes (stability TR) | lanes (split TR) | block | ms | flashes/s |",
-             "|---|---|---|---|---|---|---|"]
+             "| sets | nc | lanes (stability TR) | lanes (split TR) | lanes (substitutions) "
+             "| block | ms | flashes/s |",
+             "|---|---|---|---|---|---|---|---|"]
     t = lambda x: torch.as_tensor(x, dtype=torch.float64, device=dev).contiguous()
     for pm in (0, 1):
         for nc in range(lo, hi + 1):
@@ -134,26 +156,37 @@ def main():
                                                (200.0, 600.0), (1.0e5, 2.0e7))
             args = [t(v) for v in (w.z, w.T, w.P, w.Tc, w.Pc, w.omega, w.kij)]
             del w
-            best = None
             tag = "per mixture" if pm else "shared"
-            for (la, lb, k) in candidates(nc):
-                dt = time_one(args, la, lb, k, a.reps)
-                lines.append(f"| {tag} | {nc} | {la} | {lb} | {k} | {dt * 1e3:.3f} | "
-                             f"{n / dt / 1e6:.1f} M |")
-                print(f"{tag} nc {nc} lanes {la}/{lb} block {k}: {dt * 1e3:.3f} ms", flush=True)
-                if best is None or dt < best[0]:
-                    best = (dt, la, lb, k)
-            lanes_sa[pm][nc], lanes_sp[pm][nc], blocks[pm][nc] = best[1], best[2], best[3]
-            lines.append(f"| {tag} | **{nc}** | **{best[1]}** | **{best[2]}** | **{best[3]}** "
-                         "| chosen | |")
+            timed = {}
+
+            def timing(cfg):
+                if cfg not in timed:
+                    dt = time_one(args, *cfg, a.reps)
+                    timed[cfg] = dt
+                    lines.append(f"| {tag} | {nc} | {cfg[0]} | {cfg[1]} | {cfg[2]} | {cfg[3]} | "
+                                 f"{dt * 1e3:.3f} | {n / dt / 1e6:.1f} M |")
+                    print(f"{tag} nc {nc} lanes {cfg[0]}/{cfg[1]}/{cfg[2]} block {cfg[3]}: "
+                          f"{dt * 1e3:.3f} ms", flush=True)
+                return timed[cfg]
+
+            ls = lane_choices(nc)
+            cur = (lanes_sa[pm][nc] if lanes_sa[pm][nc] in ls else 1,
+                   lanes_sp[pm][nc] if lanes_sp[pm][nc] in ls else 1,
+                   lanes_ss[pm][nc] if lanes_ss[pm][nc] in ls else 1, blocks[pm][nc])
+            best = min(((la, lb, cur[2], cur[3]) for la in ls for lb in ls), key=timing)
+            best = min(((best[0], best[1], lss, best[3]) for lss in ls), key=timing)
+            best = min(((best[0], best[1], best[2], k) for k in BLOCKS), key=timing)
+            lanes_sa[pm][nc], lanes_sp[pm][nc], lanes_ss[pm][nc], blocks[pm][nc] = best
+            lines.append(f"| {tag} | **{nc}** | **{best[0]}** | **{best[1]}** | **{best[2]}** "
+                         f"| **{best[3]}** | chosen | |")
             del args
             torch.cuda.empty_cache()
     os.makedirs(a.out, exist_ok=True)
     with open(os.path.join(a.out, "tuned_gfx950.hpp"), "w") as f:
-        f.write(header(lanes_sa, lanes_sp, blocks))
+        f.write(header(lanes_sa, lanes_sp, lanes_ss, blocks))
     with open(os.path.join(a.out, "autotune_gfx950.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
-    print("lanes", lanes_sa, lanes_sp, "\nblocks", blocks)
+    print("lanes", lanes_sa, lanes_sp, lanes_ss, "\nblocks", blocks)
 
 
 if __name__ == "__main__":

@@ -6,11 +6,14 @@
 // Hessian, its Cholesky factor and the composition derivatives of two phases
 // per lane: 3 nc(nc+1)/2 doubles, which at nc = 20 is several KB per lane and
 // spills.  Here lane i of a group holds component i: its composition and
-// gradient entries, row i of the Hessian and row i of the factor.  Sums over
-// components are butterfly reductions inside the group (every lane ends with
-// the same bits: floating-point addition is commutative), vectors that every
-// row needs are broadcast through the group's LDS region, and the factor is
-// also kept there so that the back substitution can read its columns.  The
+// gradient entries, row i of the Hessian and row i of the factor.  Both rows
+// live in the group's LDS region, not in registers, and the loops over
+// components run rolled (a few iterations unrolled), so that the registers a
+// lane needs do not grow with nc.  Sums over components are butterfly
+// reductions inside the group (every lane ends with the same bits:
+// floating-point addition is commutative), vectors that every row needs are
+// broadcast through the LDS region, and the back substitution reads the
+// factor's columns there.  The
 // mixture's scalars (cubic root, trust radius, counters, decisions) are
 // computed identically in every lane of the group, so a group always takes
 // one path.  The arithmetic is that of the per-lane items in flash_stages.hpp
@@ -25,16 +28,21 @@ namespace ptf {
 // Component counts from which the group variants are compiled.
 constexpr int kGroupMinNc = 8;
 
-// LDS doubles of one group: the factor (nc + 1 rows of LD doubles: row i of
-// L, and a spare row that the lanes beyond nc write to) and five broadcast
-// vectors of G entries.  The row stride LD = nc + 1 is odd, so that the lanes
-// of a group, each reading its own row, fall in different banks.
+// LDS doubles of one group: the factor and the Hessian (nc + 1 rows of LD
+// doubles each: row i of L or of H, and a spare row that the lanes beyond nc
+// write to) and five broadcast vectors of G entries.  The row stride
+// LD = nc + 1 is odd, so that the lanes of a group, each reading its own row,
+// fall in different banks.
 template <int NC, int G>
 struct GroupLds {
     static constexpr int LD = NC + 1;
     static constexpr int L = 0;
-    static constexpr int V = (NC + 1) * LD;
+    static constexpr int H = (NC + 1) * LD;
+    static constexpr int V = 2 * (NC + 1) * LD;
     static constexpr int N = V + 5 * G;
+    // doubles of a group of an item with (kMatrix) or without the matrices
+    template <class Item>
+    static constexpr int of() { return Item::kMatrix ? N : 5 * G; }
 };
 
 // Orders the LDS accesses of one wavefront: stores before the fence are
@@ -76,11 +84,11 @@ __device__ __forceinline__ double gbcast(double v, int base, int j)
     return __shfl(v, base + j, 64);
 }
 
-// Lane geometry of a group and its LDS region.  The unrolled loops below
-// over components j never test gi against j (such tests are loop-invariant
-// lane masks that the compiler keeps live across the whole kernel): values
-// of one lane are broadcast from it, results are read back from LDS slots,
-// and the diagonal of a matrix row is carried separately.
+// Lane geometry of a group and its LDS region.  The loops below over
+// components j never test gi against j (such tests are loop-invariant lane
+// masks that the compiler keeps live across the whole kernel): values of one
+// lane are broadcast from it, results are read back from LDS slots, and the
+// diagonal of a matrix row is carried separately.
 template <int NC, int G>
 struct Grp {
     // all five fields are set by the kernel before the first item begins
@@ -88,16 +96,20 @@ struct Grp {
     int row;      // gi, or NC (the spare factor row) beyond the components
     int base;     // first lane of the group in the wavefront
     bool act;     // gi < NC
-    double *sh;   // GroupLds<NC, G>::N doubles
+    double *sh;   // the group's region: GroupLds<NC, G>::of<Item>() doubles
+    double *vb;   // its five broadcast vectors (after the matrices, if any)
     const double *ks;   // the block's kappa table in LDS (shared component set only)
     static constexpr int LD = GroupLds<NC, G>::LD;   // factor row stride
-    __device__ __forceinline__ double *vec(int q) const { return sh + GroupLds<NC, G>::V + q * G; }
+    __device__ __forceinline__ double *vec(int q) const { return vb + q * G; }
     __device__ __forceinline__ double *lsh() const { return sh + GroupLds<NC, G>::L; }
+    // this lane's row of H = M + diag(dadd) without the addend (row NC
+    // beyond the components)
+    __device__ __forceinline__ double *hr() const { return sh + GroupLds<NC, G>::H + row * LD; }
 };
 
 // Row gi of the table kappa_ij = 1 - k_ij of the caller's mixture: for a
 // shared component set a view of the block's table in LDS (loaded once per
-// block), for one set per mixture the row in registers.
+// block), for one set per mixture the mixture's k row in global memory.
 struct KapLds {
     // odd row stride: the lanes of a group, each on its own row, read
     // different banks
@@ -106,10 +118,9 @@ struct KapLds {
     const double *row;
     __device__ __forceinline__ double operator[](int j) const { return row[j]; }
 };
-template <int NC>
-struct KapRegs {
-    double v[NC];
-    __device__ __forceinline__ double operator[](int j) const { return v[j]; }
+struct KapGlobal {
+    const double *krow;
+    __device__ __forceinline__ double operator[](int j) const { return 1.0 - krow[j]; }
 };
 
 // Phase evaluation E(c) of one mixture across its group: this lane's share is
@@ -132,7 +143,7 @@ __device__ __forceinline__ void phase_eval_g(PhaseG &o, const Grp<NC, G> &g, dou
     tv[g.gi] = t;
     wave_lds_sync();
     double psi = 0.0;
-#pragma unroll
+#pragma unroll 4
     for (int j = 0; j < NC; ++j) psi += kap[j] * tv[j];
     wave_lds_sync();
     const double A = gsum<G>(g.act ? t * psi : 0.0);
@@ -150,11 +161,12 @@ __device__ __forceinline__ void phase_eval_g(PhaseG &o, const Grp<NC, G> &g, dou
 }
 
 // Adds wrow * v_j * Phi_ij (row i = gi of Phi = n d ln phi / d n, as
-// phase_derivs) to hrow[j] for every j, and the diagonal term to hdiag (the
-// same bits as hrow[gi]); v is this lane's entry of the scaling vector (0 on
-// inactive lanes, where wrow is 0 too).
-template <int NC, int G, class Kap>
-__device__ __forceinline__ void phase_derivs_g(double (&hrow)[NC], double &hdiag, const PhaseG &o,
+// phase_derivs) to this lane's LDS row of H, entry j for every j (ACC
+// false: stores it there), and the diagonal term to hdiag (the same bits as
+// entry gi); v is this lane's entry of the scaling vector (0 on inactive
+// lanes, where wrow is 0 too).
+template <bool ACC, int NC, int G, class Kap>
+__device__ __forceinline__ void phase_derivs_g(double &hdiag, const PhaseG &o,
                                                const Grp<NC, G> &g, double s, double b,
                                                const Kap &kap, double wrow, double v,
                                                uint32_t &fl)
@@ -184,10 +196,12 @@ __device__ __forceinline__ void phase_derivs_g(double (&hrow)[NC], double &hdiag
     wave_lds_sync();
     const double cst = o.q2 * sp;
     const double qs = o.q2 * s;
-#pragma unroll
+    double *hr = g.hr();
+#pragma unroll 4
     for (int j = 0; j < NC; ++j) {
         const double phi = b * va[j] - vb[j] - sp * vg[j] + cst - qs * kap[j] * vs[j];
-        hrow[j] += wrow * vv[j] * phi;
+        const double add = wrow * vv[j] * phi;
+        hr[j] = ACC ? hr[j] + add : 0.0 + add;
     }
     wave_lds_sync();
     // kappa_ii = 1 - k_ii = 1 (a valid set has a zero diagonal)
@@ -196,25 +210,27 @@ __device__ __forceinline__ void phase_derivs_g(double (&hrow)[NC], double &hdiag
     fl += Cost<NC>::derivs;
 }
 
-// Cholesky factor of H + shift I, H = M + diag(dadd) with M given by rows
-// (hrow) and dadd this lane's diagonal addend: the factor in the group's LDS,
-// row gi by this lane (entries past the diagonal are not meaningful; the
-// diagonal is written by lane j at step j), 1/L_ii of this row in dinv.
-// Returns whether every pivot was positive (the same in every lane).  As
-// cholesky.
+// Cholesky factor of H + shift I, H = M + diag(dadd) with M given by the
+// LDS rows (g.hr()) and dadd this lane's diagonal addend: the factor in the
+// group's LDS, row gi by this lane (entries past the diagonal are not
+// meaningful; the diagonal is written by lane j at step j), 1/L_ii of this
+// row in dinv.  Returns whether every pivot was positive (the same in every
+// lane).  As cholesky.
 template <int NC, int G>
-__device__ __forceinline__ bool chol_g(double &dinv, const double (&hrow)[NC], double dadd,
-                                       double shift, const Grp<NC, G> &g, uint32_t &fl)
+__device__ __forceinline__ bool chol_g(double &dinv, double dadd, double shift,
+                                       const Grp<NC, G> &g, uint32_t &fl)
 {
     constexpr int LD = Grp<NC, G>::LD;
     double *Ls = g.lsh();
     double *mine = Ls + g.row * LD;
+    const double *hr = g.hr();
     bool ok = true;
-#pragma unroll
+#pragma unroll 1
     for (int j = 0; j < NC; ++j) {
-        double s = hrow[j];
-#pragma unroll
-        for (int k = 0; k < j; ++k) s -= mine[k] * Ls[j * LD + k];
+        double s = hr[j];
+        const double *lj = Ls + j * LD;
+#pragma unroll 4
+        for (int k = 0; k < j; ++k) s -= mine[k] * lj[k];
         // lane j's s is the pivot (before its diagonal terms)
         const double piv = gbcast(s + dadd, g.base, j) + shift;
         ok = ok && (piv > 0.0);
@@ -236,7 +252,7 @@ __device__ __forceinline__ double lower_solve_g(double dinv, double b, const Grp
     const double *mine = g.lsh() + g.row * Grp<NC, G>::LD;
     double *yv = g.vec(1);
     double r = b;
-#pragma unroll
+#pragma unroll 2
     for (int j = 0; j < NC; ++j) {
         const double yj = gbcast(r * dinv, g.base, j);
         yv[j] = yj;
@@ -256,7 +272,7 @@ __device__ __forceinline__ double upper_solve_g(double dinv, double y, const Grp
     double *xv = g.vec(2);
     const int col = g.act ? g.gi : 0;
     double r = y;
-#pragma unroll
+#pragma unroll 2
     for (int k = NC - 1; k >= 0; --k) {
         const double xk = gbcast(r * dinv, g.base, k);
         xv[k] = xk;
@@ -270,28 +286,27 @@ __device__ __forceinline__ double upper_solve_g(double dinv, double y, const Grp
 
 // (H v)_i = sum_j M_ij v_j + dadd_i v_i from this lane's row and the group's v.
 template <int NC, int G>
-__device__ __forceinline__ double hv_g(const double (&hrow)[NC], double dadd, double v,
-                                       const Grp<NC, G> &g)
+__device__ __forceinline__ double hv_g(double dadd, double v, const Grp<NC, G> &g)
 {
     double *vv = g.vec(0);
+    const double *hr = g.hr();
     vv[g.gi] = v;
     wave_lds_sync();
     double r = 0.0;
-#pragma unroll
-    for (int j = 0; j < NC; ++j) r += hrow[j] * vv[j];
+#pragma unroll 4
+    for (int j = 0; j < NC; ++j) r += hr[j] * vv[j];
     wave_lds_sync();
     return r + dadd * v;
 }
 
 // Trust-region step of Hebden type across the group: as trust_step, with
-// this lane's entries of u and g, row of M and diagonal term (H = M +
-// diag(dadd), M_ii = hdiag); the group's LDS holds the last factor, dinv
-// this lane's 1/L_ii.  newton_only as in trust_step.
+// this lane's entries of u and g, row of M in LDS (g.hr()) and diagonal term
+// (H = M + diag(dadd), M_ii = hdiag); the group's LDS holds the last factor,
+// dinv this lane's 1/L_ii.  newton_only as in trust_step.
 template <int NC, int G>
 __device__ __forceinline__ double trust_step_g(double &u, double &radius, bool &eta0,
-                                               double &dinv, const double (&hrow)[NC],
-                                               double hdiag, double dadd, double gv,
-                                               const Grp<NC, G> &g, uint32_t &fl,
+                                               double &dinv, double hdiag, double dadd,
+                                               double gv, const Grp<NC, G> &g, uint32_t &fl,
                                                bool newton_only = false)
 {
     const double mg = -gv;
@@ -299,7 +314,7 @@ __device__ __forceinline__ double trust_step_g(double &u, double &radius, bool &
     bool have = false;
     double eta1 = -1.0;
     u = 0.0;
-    if (chol_g<NC, G>(dinv, hrow, dadd, 0.0, g, fl)) {
+    if (chol_g<NC, G>(dinv, dadd, 0.0, g, fl)) {
         const double y = lower_solve_g<NC, G>(dinv, mg, g);
         u = upper_solve_g<NC, G>(dinv, y, g);
         fl += Cost<NC>::trisolve;
@@ -320,8 +335,9 @@ __device__ __forceinline__ double trust_step_g(double &u, double &radius, bool &
     if (newton_only) return 0.0;
     if (!have) {
         double rs = 0.0;
-#pragma unroll
-        for (int j = 0; j < NC; ++j) rs += fabs(hrow[j]);
+        const double *hr = g.hr();
+#pragma unroll 4
+        for (int j = 0; j < NC; ++j) rs += fabs(hr[j]);
         rs += fabs(hdiag + dadd) - fabs(hdiag);
         const double hmin = gmin<G>(g.act ? hdiag + dadd : INFINITY);
         const double rowmax = gmax<G>(g.act ? rs : 0.0);
@@ -330,7 +346,7 @@ __device__ __forceinline__ double trust_step_g(double &u, double &radius, bool &
         double eta = elo > 0.0 ? elo : 1e-3 * ehi;
         if (eta1 > 0.0 && eta1 < ehi) eta = eta1;
         for (int it = 0; it < 12; ++it) {
-            if (!chol_g<NC, G>(dinv, hrow, dadd, eta, g, fl)) {
+            if (!chol_g<NC, G>(dinv, dadd, eta, g, fl)) {
                 elo = eta;
                 eta = fmax(sqrt(elo * ehi), elo + 1e-3 * (ehi - elo));
                 continue;
@@ -350,7 +366,7 @@ __device__ __forceinline__ double trust_step_g(double &u, double &radius, bool &
             eta = en;
         }
         if (!have) {
-            const double hg = hv_g<NC, G>(hrow, dadd, gv, g);
+            const double hg = hv_g<NC, G>(dadd, gv, g);
             const double gg = gsum<G>(gv * gv);
             const double ghg = gsum<G>(gv * hg);
             const double tmax = radius / sqrt(gg);
@@ -359,7 +375,7 @@ __device__ __forceinline__ double trust_step_g(double &u, double &radius, bool &
             fl += 2 * NC * NC + 4 * NC;
         }
     }
-    const double hu = hv_g<NC, G>(hrow, dadd, u, g);
+    const double hu = hv_g<NC, G>(dadd, u, g);
     const double gu = gsum<G>(gv * u);
     const double uhu = gsum<G>(u * hu);
     fl += 2 * NC * NC + 2 * NC;
@@ -375,15 +391,342 @@ __device__ __forceinline__ auto kappa_of(const Ctx<NC> &c, int64_t m, const Grp<
 {
     const int row = g.act ? g.gi : 0;
     if constexpr (PM) {
-        const Props pp = mix_props<NC, PM>(c.pr, m);
-        KapRegs<NC> k;
-#pragma unroll
-        for (int j = 0; j < NC; ++j) k.v[j] = 1.0 - pp.K[row * NC + j];
-        return k;
+        return KapGlobal{mix_props<NC, PM>(c.pr, m).K + row * NC};
     } else {
         return KapLds{g.ks + row * KapLds::stride<NC>()};
     }
 }
+
+// One substitution update with acceleration across the group (as
+// ss_update): this lane's entries v, prev, s; returns ext.
+template <int NC, int G>
+__device__ __forceinline__ double ss_update_g(double &v, double &prev, double s, int u, int dem,
+                                              uint32_t &fl)
+{
+    double ext = 0.0;
+    if (dem > 0 && u >= 2 && (u % dem) == 0) {
+        const double num = gsum<G>(s * s), den = gsum<G>(prev * s);
+        const double lam = num / den;
+        if (lam > 0.0 && lam < 1.0) ext = lam / (1.0 - lam);
+        fl += 4 * NC + 3;
+    }
+    v += s + ext * s;
+    prev = s;
+    fl += 3 * NC;
+    return ext;
+}
+
+// Rachford-Rice across the group (as rr_solve; this lane's z_i and K_i, 0
+// and 1 on inactive lanes).  Every lane takes the same iterates.
+template <int NC, int G>
+__device__ __forceinline__ bool rr_solve_g(double z, double K, double &th, const Grp<NC, G> &g,
+                                           uint32_t &fl)
+{
+    const double kmax = gmax<G>(g.act ? K : -INFINITY);
+    const double kmin = gmin<G>(g.act ? K : INFINITY);
+    if (!(kmax > 1.0) || !(kmin < 1.0)) return false;
+    const double al = 1.0 / (1.0 - kmax), ar = 1.0 / (1.0 - kmin);
+    double lo = al, hi = ar;
+    double t = (th > al && th < ar) ? th : 0.5;
+    const double c = K - 1.0;
+    int it = 0;
+    for (; it < 200; ++it) {
+        const double r = 1.0 / (1.0 + c * t);
+        const double u = z * c * r;
+        const double f = gsum<G>(u);
+        const double fp = -gsum<G>(u * c * r);
+        if (f > 0.0) lo = t; else hi = t;
+        const double da = t - al, db = ar - t;
+        const double h = da * db * f;
+        const double hp = (db - da) * f + da * db * fp;
+        const double tn = t - h / hp;
+        if (fabs(tn - t) < 1e-8) {
+            t = fmin(fmax(tn, lo), hi);
+            break;
+        }
+        t = (tn > lo && tn < hi) ? tn : 0.5 * (lo + hi);
+        if (!(hi - lo > 0.0)) break;
+    }
+    fl += Cost<NC>::rr_iter * (uint32_t)(it + 1);
+    th = t;
+    return true;
+}
+
+// K -> Rachford-Rice -> normalised x, y across the group (as xy_from_lnk).
+template <int NC, int G>
+__device__ __forceinline__ bool xy_from_lnk_g(double &x, double &y, double lnk, double z,
+                                              double &theta, const Grp<NC, G> &g, uint32_t &fl)
+{
+    const double K = g.act ? exp(lnk) : 1.0;
+    fl += NC;
+    if (!rr_solve_g<NC, G>(z, K, theta, g, fl)) return false;
+    const double xr = z / (1.0 + theta * (K - 1.0));
+    const double yr = K * xr;
+    const double sx = gsum<G>(xr), sy = gsum<G>(yr);
+    x = xr * (1.0 / sx);
+    y = yr * (1.0 / sy);
+    fl += 8 * NC + 2;
+    return true;
+}
+
+// The feed normalised with the sum taken in component order (as load_z):
+// this lane's z_i, 0 on inactive lanes.
+template <int NC, int G>
+__device__ __forceinline__ double load_z_g(const FlashArgs &a, int64_t m, const Grp<NC, G> &g)
+{
+    double sz = 0.0;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) sz += a.z[m * NC + j];
+    return g.act ? a.z[m * NC + g.gi] / sz : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// SaSs with one group per trial (as SaSsItem)
+// ---------------------------------------------------------------------------
+template <int NC, bool PM, int G>
+struct SaSsGroup {
+    static constexpr int WAVES = 2;   // minimum wavefronts per SIMD
+    static constexpr bool kPerMixture = PM;   // one component set per mixture
+    static constexpr uint32_t OUT = 1u << L_SATR;   // lists the steps append to
+    Outbox ob;   // list entries produced by the current step (lane gi = 0)
+    static constexpr int LIST = L_SA;
+    static constexpr int LIST2 = -1;
+    static constexpr bool kMatrix = false;   // LDS: broadcast vectors only
+    int64_t m;
+    int t;
+    double lw, prev, d, s, b;   // this lane's component
+    double tmb, ext, zw;
+    bool dem;
+    int ss, steps;
+    uint32_t fl, st;
+
+    __device__ __forceinline__ bool begin(const Ctx<NC> &c, uint32_t id, const Grp<NC, G> &g)
+    {
+        m = id >> 1;
+        t = (int)(id & 1u);
+        const MixRec<NC> &r = c.rec[m];
+        const int i = g.act ? g.gi : 0;
+        s = g.act ? r.s[i] : 0.0;
+        b = g.act ? r.b[i] : 0.0;
+        d = g.act ? r.d[i] : 0.0;
+        lw = g.act ? (t == 0 ? r.lnz[i] + r.lkw[i] : r.lnz[i] - r.lkw[i]) : 0.0;
+        prev = 0.0;
+        fl = 2 * NC;
+        st = 0;
+        ss = 0;
+        steps = 0;
+        dem = false;
+        zw = -1.0;
+        return true;
+    }
+
+    __device__ __forceinline__ void done(const Ctx<NC> &c, double tm, bool to_tr,
+                                         const Grp<NC, G> &g)
+    {
+        MixRec<NC> &r = c.rec[m];
+        if (g.act) r.lw[t][g.gi] = lw;
+        if (g.gi == 0) {
+            r.tm[t] = tm;
+            r.it[t == 0 ? 1 : 3] = (int16_t)ss;
+            r.it[t == 0 ? 2 : 4] = 0;
+            r.tfl[t] = fl;
+            r.tst[t] = st;
+            if (to_tr) ob.put(L_SATR, (uint32_t)(2 * m + t));
+        }
+    }
+
+    __device__ __forceinline__ bool step(const Ctx<NC> &c, const Grp<NC, G> &g)
+    {
+        const FlashArgs &a = c.a;
+        const auto kap = kappa_of<NC, PM, G>(c, m, g);
+        const double W = g.act ? exp(lw) : 0.0;
+        fl += NC;
+        PhaseG o;
+        phase_eval_g<NC, G>(o, g, s, b, kap, W, fl, zw);
+        zw = o.Z;
+        const double grad = g.act ? lw + o.lnphi - d : 0.0;
+        const double tm = 1.0 + gsum<G>(W * (grad - 1.0));
+        const double gmx = gmax<G>(fabs(grad));
+        fl += 6 * NC;
+        if (tm < -a.eps_tm || gmx < a.tol_sa_ss) {
+            done(c, tm, false, g);
+            return true;
+        }
+        if (dem) {
+            // an extrapolated point is kept only if it lowers tm
+            dem = false;
+            if (!(tm < tmb)) {
+                lw -= ext * prev;
+                if (++steps < kStepGuard) return false;
+            }
+        }
+        if (ss < a.max_ss && ++steps < kStepGuard) {
+            ext = ss_update_g<NC, G>(lw, prev, -grad, ss + 1, a.dem_every, fl);
+            ++ss;
+            if (ext > 0.0) {
+                dem = true;
+                tmb = tm;
+            }
+            return false;
+        }
+        // substitution budget spent: continue with the trust region
+        done(c, tm, true, g);
+        return true;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// SpSs with one group per split (as SpSsItem)
+// ---------------------------------------------------------------------------
+template <int NC, bool PM, int G>
+struct SpSsGroup {
+    static constexpr int WAVES = 2;   // minimum wavefronts per SIMD
+    static constexpr bool kPerMixture = PM;   // one component set per mixture
+    static constexpr uint32_t OUT = (1u << L_NT) | (1u << L_NTP);
+    Outbox ob;   // list entries produced by the current step (lane gi = 0)
+    static constexpr int LIST = L_SPLIT;
+    static constexpr int LIST2 = -1;
+    static constexpr bool kMatrix = false;   // LDS: broadcast vectors only
+    int64_t m;
+    double z, lk, prev, s, b;   // this lane's component
+    double theta, sgb, sext, zx, zy;
+    bool dem;
+    int ss, steps;
+    uint32_t fl, status;
+
+    __device__ __forceinline__ bool begin(const Ctx<NC> &c, uint32_t id, const Grp<NC, G> &g)
+    {
+        m = id;
+        const MixRec<NC> &r = c.rec[m];
+        const int i = g.act ? g.gi : 0;
+        z = load_z_g<NC, G>(c.a, m, g);
+        s = g.act ? r.s[i] : 0.0;
+        b = g.act ? r.b[i] : 0.0;
+        lk = g.act ? r.lk[i] : 0.0;
+        prev = 0.0;
+        theta = r.theta;
+        fl = r.fl;
+        status = r.status;
+        ss = 0;
+        steps = 0;
+        dem = false;
+        zx = zy = -1.0;
+        return true;
+    }
+
+    __device__ __forceinline__ void fail(const Ctx<NC> &c, uint32_t bits, const Grp<NC, G> &g)
+    {
+        const FlashArgs &a = c.a;
+        const MixRec<NC> &r = c.rec[m];
+        if (g.act) {
+            a.x[m * NC + g.gi] = z;
+            a.y[m * NC + g.gi] = z;
+        }
+        if (g.gi == 0) {
+            a.label[m] = 0;
+            a.beta[m] = -1.0;
+            if (a.iters) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) a.iters[m * 8 + k] = k == 5 ? (int16_t)ss : r.it[k];
+            }
+            if (a.status) a.status[m] = (uint16_t)(status | bits);
+            if (a.flops) a.flops[m] = fl;
+        }
+    }
+
+    // As SpSsItem::restart_or_fail.
+    __device__ __forceinline__ void restart_or_fail(const Ctx<NC> &c, bool no_root,
+                                                    uint32_t fail_bits, const Grp<NC, G> &g)
+    {
+        MixRec<NC> &r = c.rec[m];
+        if (r.wsel < 0) {
+            fail(c, kStSplitFailed | (no_root ? kStRrNoRoot : 0u) | fail_bits, g);
+            return;
+        }
+        if (g.gi == 0) {
+            r.rst = no_root ? 2 : 1;
+            r.it[5] = (int16_t)ss;
+            r.fl = fl;
+            r.status = status | kStSplitTr | kStSplitRestart;
+            ob.put(L_NT, (uint32_t)m);
+        }
+    }
+
+    __device__ __forceinline__ bool step(const Ctx<NC> &c, const Grp<NC, G> &g)
+    {
+        const FlashArgs &a = c.a;
+        const auto kap = kappa_of<NC, PM, G>(c, m, g);
+        double x, y;
+        if (!xy_from_lnk_g<NC, G>(x, y, lk, z, theta, g, fl)) {
+            if (dem) {
+                // an extrapolated point without a Rachford-Rice root is
+                // rejected like one that does not lower G
+                dem = false;
+                lk -= sext * prev;
+                if (++steps < kStepGuard) return false;
+            }
+            restart_or_fail(c, true, 0u, g);
+            return true;
+        }
+        PhaseG o;
+        phase_eval_g<NC, G>(o, g, s, b, kap, x, fl, zx);
+        zx = o.Z;
+        const double r0 = o.lnphi;
+        phase_eval_g<NC, G>(o, g, s, b, kap, y, fl, zy);
+        zy = o.Z;
+        // G per unit feed (eq. gibbs) where an acceleration check needs it
+        const bool dem_next = a.dem_every > 0 && ss + 1 >= 2 && ((ss + 1) % a.dem_every) == 0;
+        double G_ = 0.0;
+        if (dem || dem_next) {
+            G_ = gsum<G>(g.act ? (1.0 - theta) * x * (log(x) + r0) + theta * y * (log(y) + o.lnphi)
+                               : 0.0);
+            fl += 10 * NC;
+        }
+        if (dem) {
+            // an extrapolated point is kept only if it is a physical split and
+            // lowers G
+            dem = false;
+            if (!(theta > 0.0 && theta < 1.0 && G_ < sgb)) {
+                lk -= sext * prev;
+                if (++steps < kStepGuard) return false;
+            }
+        }
+        const double sv = g.act ? (r0 - o.lnphi) - lk : 0.0;
+        const double dmax = gmax<G>(g.act ? fabs(exp(sv) - 1.0) : 0.0);
+        fl += 4 * NC;
+        const bool conv = dmax < a.tol_split_ss;
+        const bool more = !conv && ss + 1 < a.max_ss && steps + 1 < kStepGuard;
+        const double ext = ss_update_g<NC, G>(lk, prev, sv, ss + 1, more ? a.dem_every : 0, fl);
+        ++ss;
+        if (more) {
+            ++steps;
+            if (ext > 0.0) {
+                dem = true;
+                sgb = G_;
+                sext = ext;
+            }
+            return false;
+        }
+        // hand over to the trust region: n^V = theta y from the final K
+        MixRec<NC> &r = c.rec[m];
+        if (!xy_from_lnk_g<NC, G>(x, y, lk, z, theta, g, fl)) {
+            restart_or_fail(c, true, conv ? 0u : kStSplitTr, g);
+            return true;
+        }
+        if (!(theta > 0.0 && theta < 1.0)) {
+            restart_or_fail(c, false, conv ? 0u : kStSplitTr, g);
+            return true;
+        }
+        if (g.act) r.lk[g.gi] = theta * y;
+        if (g.gi == 0) {
+            r.it[5] = (int16_t)ss;
+            r.fl = fl;
+            r.status = status | (conv ? 0u : kStSplitTr);
+            ob.put(conv ? L_NTP : L_NT, (uint32_t)m);
+        }
+        return true;
+    }
+};
 
 // ---------------------------------------------------------------------------
 // SaTr with one group per trial (as SaTrItem)
@@ -395,6 +738,7 @@ struct SaTrGroup {
     static constexpr uint32_t OUT = 0u;
     static constexpr int LIST = L_SATR;
     static constexpr int LIST2 = -1;
+    static constexpr bool kMatrix = true;   // LDS: Hessian and factor rows
     int64_t m;
     int t;
     double lw, lacc, d, s, b;   // this lane's component
@@ -485,15 +829,13 @@ struct SaTrGroup {
         }
         // H_ij = delta_ij (1 + grad_i/2) + sqrt(c_i c_j) Phi_ij
         const double rc = sqrt(W / sw);
-        double hrow[NC], hdiag = 0.0;
-#pragma unroll
-        for (int j = 0; j < NC; ++j) hrow[j] = 0.0;
-        phase_derivs_g<NC, G>(hrow, hdiag, o, g, s, b, kap, rc, rc, fl);
+        double hdiag = 0.0;
+        phase_derivs_g<false>(hdiag, o, g, s, b, kap, rc, rc, fl);
         const double dadd = 1.0 + 0.5 * grad;
         fl += 2 * Tri<NC>::N + 4 * NC;
         double dinv = 0.0, u;
         bool eta0;
-        double pr = trust_step_g<NC, G>(u, rad, eta0, dinv, hrow, hdiag, dadd, gv, g, fl);
+        double pr = trust_step_g<NC, G>(u, rad, eta0, dinv, hdiag, dadd, gv, g, fl);
         const double bi = 2.0 * sqrt(W);
         const double amax = gmin<G>((g.act && u < 0.0) ? fmin(1.0, 0.99 * bi / -u) : 1.0);
         slen = amax * sqrt(gsum<G>(g.act ? u * u : 0.0));
@@ -523,6 +865,7 @@ struct SpNtGroup {
     static constexpr uint32_t OUT = 0u;
     static constexpr int LIST = L_NT;
     static constexpr int LIST2 = L_NTP;
+    static constexpr bool kMatrix = true;   // LDS: Hessian and factor rows
     static constexpr int NP = Tri<NC>::N;
     int64_t m;
     double z, v0, v1, s, b;   // this lane's component
@@ -679,20 +1022,18 @@ struct SpNtGroup {
         // v_i = sqrt(x_i y_i / z_i)
         const double vs = g.act ? sqrt(w0 * w1 / z) : 0.0;
         fl += 4 * NC;
-        double hrow[NC], hdiag = 0.0, dinv = 0.0;
-#pragma unroll
-        for (int j = 0; j < NC; ++j) hrow[j] = 0.0;
+        double hdiag = 0.0, dinv = 0.0;
         PhaseG o;
         phase_eval_g<NC, G>(o, g, s, b, kap, w0, fl, zx);
         zx = o.Z;
         const double th = bvap;
-        phase_derivs_g<NC, G>(hrow, hdiag, o, g, s, b, kap, th * vs, vs, fl);
+        phase_derivs_g<false>(hdiag, o, g, s, b, kap, th * vs, vs, fl);
         fl += 3 * NP;
         const double r0 = o.lnphi;
         const double Z0 = o.Z;
         phase_eval_g<NC, G>(o, g, s, b, kap, w1, fl, zy);
         zy = o.Z;
-        phase_derivs_g<NC, G>(hrow, hdiag, o, g, s, b, kap, (1.0 - th) * vs, vs, fl);
+        phase_derivs_g<true>(hdiag, o, g, s, b, kap, (1.0 - th) * vs, vs, fl);
         // gradient of G over n^V (eq. split_grad) and G itself (eq. gibbs)
         const double fx = g.act ? log(w0) + r0 : 0.0;
         const double fy = g.act ? log(w1) + o.lnphi : 0.0;
@@ -725,10 +1066,11 @@ struct SpNtGroup {
         const double sc = 1.0 / (th * (1.0 - th));
         {
             double *vv = g.vec(0);
+            double *hr = g.hr();
             vv[g.gi] = vs;
             wave_lds_sync();
-#pragma unroll
-            for (int j = 0; j < NC; ++j) hrow[j] = g.act ? (hrow[j] - vs * vv[j]) * sc : 0.0;
+#pragma unroll 4
+            for (int j = 0; j < NC; ++j) hr[j] = g.act ? (hr[j] - vs * vv[j]) * sc : 0.0;
             wave_lds_sync();
         }
         // the identity term of H' is the diagonal addend sc
@@ -776,8 +1118,7 @@ struct SpNtGroup {
         double u;
         bool eta0;
         double rad = newton ? 1e300 : srad;
-        double pr = trust_step_g<NC, G>(u, rad, eta0, dinv, hrow, hdiag, dadd, gs, g, fl,
-                                        newton);
+        double pr = trust_step_g<NC, G>(u, rad, eta0, dinv, hdiag, dadd, gs, g, fl, newton);
         if (newton && !eta0) {
             spol = false;
             tronly = true;

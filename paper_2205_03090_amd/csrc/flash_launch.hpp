@@ -17,6 +17,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <vector>
+
 #include "flash_api.hpp"
 #include "flash_stages.hpp"
 #include "flash_group.hpp"
@@ -259,21 +262,24 @@ stage_persistent(Ctx<NC> c, const double *__restrict__ Tc, const double *__restr
 
 // Persistent stage with one group of G lanes per item (flash_group.hpp): as
 // stage_persistent, with groups in place of lanes.  The lowest lane of each
-// group takes part in the claim; the items of these stages append to no
-// list.
+// group takes part in the claim and holds the group's list entries.
 template <class Item, int NC, int G>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(Item::WAVES)))
 stage_persistent_group(Ctx<NC> c, const double *__restrict__ Tc, const double *__restrict__ Pc,
                        const double *__restrict__ om, const double *__restrict__ K,
                        unsigned long long *__restrict__ take)
 {
-    static_assert(Item::OUT == 0u, "group items append to no list");
     static_assert(64 % G == 0 && G >= NC, "a group spans the components within one wavefront");
-    __shared__ double group_lds[kBlock / G][GroupLds<NC, G>::N];
-    // a shared component set: the table kappa_ij = 1 - k_ij once per block,
-    // rows KapLds::stride<NC>() apart
+    constexpr uint32_t OUT = Item::OUT;
+    constexpr int NOUT = popcount32(OUT) > 0 ? popcount32(OUT) : 1;
+    __shared__ uint32_t stage_buf[kWavesPerBlock][NOUT][kStage];
+    // dynamic LDS (group_lds_bytes): for a shared component set the table
+    // kappa_ij = 1 - k_ij, once per block with rows KapLds::stride<NC>()
+    // apart, then the region of each group of the block
+    extern __shared__ double group_dyn[];
     constexpr int KS = KapLds::stride<NC>();
-    __shared__ double kap_lds[Item::kPerMixture ? 1 : NC * KS];
+    constexpr int KN = Item::kPerMixture ? 0 : NC * KS;
+    double *kap_lds = group_dyn;
     c.pr = Props{Tc, Pc, om, K};
     if constexpr (!Item::kPerMixture) {
         for (int t = (int)threadIdx.x; t < NC * NC; t += (int)blockDim.x)
@@ -287,8 +293,13 @@ stage_persistent_group(Ctx<NC> c, const double *__restrict__ Tc, const double *_
     g.base = lane - g.gi;
     g.act = g.gi < NC;
     g.row = g.act ? g.gi : NC;
-    g.sh = group_lds[threadIdx.x / G];
+    g.sh = group_dyn + KN + (threadIdx.x / G) * GroupLds<NC, G>::template of<Item>();
+    g.vb = g.sh + (Item::kMatrix ? GroupLds<NC, G>::V : 0);
     g.ks = Item::kPerMixture ? nullptr : kap_lds;
+    uint32_t(*buf)[kStage] = stage_buf[threadIdx.x / 64];
+    int fill[NOUT];
+#pragma unroll
+    for (int l = 0; l < NOUT; ++l) fill[l] = 0;
     Claim cl(count, (unsigned long long)gridDim.x * (blockDim.x / 64),
              (unsigned long long)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64);
     Item it;
@@ -306,7 +317,79 @@ stage_persistent_group(Ctx<NC> c, const double *__restrict__ Tc, const double *_
             }
         }
         if (__ballot(!gone) == 0ull) break;
+        if constexpr (OUT != 0u) it.ob.clear();
         if (live) live = !it.step(c, g);
+        if constexpr (OUT != 0u) {
+#pragma unroll
+            for (int l = 0; l < L_COUNT; ++l) {
+                if ((OUT >> l) & 1u) {
+                    const int q = slot_of<OUT>(l);
+                    stage_slot(c.L, l, it.ob.l0, it.ob.i0, it.ob.n0, buf[q], fill[q], lane);
+                    stage_slot(c.L, l, it.ob.l1, it.ob.i1, 1, buf[q], fill[q], lane);
+                }
+            }
+        }
+    }
+    if constexpr (OUT != 0u) {
+#pragma unroll
+        for (int l = 0; l < L_COUNT; ++l) {
+            if ((OUT >> l) & 1u) {
+                const int q = slot_of<OUT>(l);
+                if (fill[q] > 0) flush_list(c.L, l, buf[q], fill[q], lane);
+            }
+        }
+    }
+}
+
+// Fused form (small batches): one lane carries one mixture through every
+// stage in the staged order, with no lists and no barrier between the
+// stages.  The items are those of the staged forms, run back to back; the
+// list entries an item's last step produces name the item that runs next.
+// Every item reads and writes only its own mixture's record, so the results
+// are those of the staged forms bit for bit; the time is that of the
+// slowest mixture's whole path instead of the sum over stages of each
+// stage's slowest item.
+template <class Item, int NC>
+__device__ __forceinline__ void fused_item(const Ctx<NC> &c, uint32_t id, Outbox &next)
+{
+    Item it;
+    next.clear();
+    if (!it.begin(c, id)) return;
+    for (;;) {
+        it.ob.clear();
+        const bool done = it.step(c);
+        if (done) {
+            next = it.ob;
+            return;
+        }
+    }
+}
+
+template <int NC, bool PM>
+__global__ void __launch_bounds__(kBlock)
+stage_fused(Ctx<NC> c, const double *__restrict__ Tc, const double *__restrict__ Pc,
+            const double *__restrict__ om, const double *__restrict__ K)
+{
+    c.pr = Props{Tc, Pc, om, K};
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= c.a.n) return;
+    const uint32_t id = (uint32_t)m;
+    Outbox o;
+    fused_item<FeedItem<NC, PM>, NC>(c, id, o);
+    if (o.l0 == L_PRE) fused_item<PreSsItem<NC, PM>, NC>(c, id, o);
+    if (o.l0 == L_SA) {
+        // the two stability trials, then the decision (list L_SAFIN)
+        for (uint32_t t = 0; t < 2; ++t) {
+            Outbox q;
+            fused_item<SaSsItem<NC, PM>, NC>(c, 2 * id + t, q);
+            if (q.l0 == L_SATR) fused_item<SaTrItem<NC, PM>, NC>(c, 2 * id + t, q);
+        }
+        fused_item<SaFinItem<NC, PM>, NC>(c, id, o);
+    }
+    if (c.a.stability_only) return;
+    if (o.l0 == L_SPLIT) {
+        fused_item<SpSsItem<NC, PM>, NC>(c, id, o);
+        if (o.l0 == L_NT || o.l0 == L_NTP) fused_item<SpNtItem<NC, PM>, NC>(c, id, o);
     }
 }
 
@@ -520,14 +603,33 @@ flash_backward_kernel(BwdArgs a, const double *__restrict__ Tc0, const double *_
 // Host side
 // ---------------------------------------------------------------------------
 
-int device_cus()
+// Resident blocks of one kernel on the current device (blocks per CU times
+// CUs) for a block size and dynamic LDS bytes, queried once per kernel,
+// device and block size and then kept.
+int resident_blocks(const void *kernel, int block, size_t lds = 0)
 {
+    struct Entry {
+        const void *kernel;
+        int dev, block, blocks;
+    };
+    static std::mutex mu;
+    static std::vector<Entry> cache;
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return 0;
-    return cus;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (const Entry &e : cache)
+            if (e.kernel == kernel && e.dev == dev && e.block == block) return e.blocks;
+    }
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        return -1;
+    const int blocks = (per_cu > 0 ? per_cu : 1) * cus;
+    std::lock_guard<std::mutex> lk(mu);
+    cache.push_back(Entry{kernel, dev, block, blocks});
+    return blocks;
 }
 
 
@@ -594,15 +696,18 @@ void setup_ctx(Ctx<NC> &c, const FlashArgs &a, int64_t n, void *ws, char **tail)
     *tail = cv.p;
 }
 
-int grid_for(const void *kernel, int block, int requested)
+// Grid of a persistent stage: the requested size, else every block the
+// device holds at once, but no more blocks than it takes to give each of
+// the stage's items (at most two per mixture: the two stability trials)
+// its lanes, so that a small batch runs on few wavefronts.
+int grid_for(const void *kernel, int block, int requested, int64_t n, int lanes_per_item,
+             size_t lds = 0)
 {
     if (requested > 0) return requested;
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess)
-        return -1;
-    const int cus = device_cus();
-    if (cus <= 0) return -1;
-    return (per_cu > 0 ? per_cu : 1) * cus;
+    const int full = resident_blocks(kernel, block, lds);
+    if (full <= 0) return -1;
+    const int64_t need = (2 * n * lanes_per_item + block - 1) / block;
+    return (int)(need < 1 ? 1 : need < full ? need : full);
 }
 
 template <class Item, int NC>
@@ -611,11 +716,19 @@ int run_persistent_stage(const Ctx<NC> &c, const ptflash_problem *p,
 {
     const int block = o->block > 0 ? o->block : tuned_block(NC, Item::kPerMixture);
     if (block % 64 != 0 || block > kBlock) return PTFLASH_EINVAL;
-    const int grid = grid_for((const void *)stage_persistent<Item, NC>, block, o->grid);
+    const int grid = grid_for((const void *)stage_persistent<Item, NC>, block, o->grid, p->n, 1);
     if (grid <= 0) return PTFLASH_EHIP;
     hipLaunchKernelGGL((stage_persistent<Item, NC>), dim3(grid), dim3(block), 0, s, c, p->Tc,
                        p->Pc, p->omega, p->kij, c.L.cnt(take_slot));
     return hipGetLastError() == hipSuccess ? PTFLASH_OK : PTFLASH_EHIP;
+}
+
+// Dynamic LDS bytes of a group stage block of the given size.
+template <class Item, int NC, int G>
+size_t group_lds_bytes(int block)
+{
+    const size_t kn = Item::kPerMixture ? 0 : (size_t)NC * KapLds::stride<NC>();
+    return 8 * (kn + (size_t)(block / G) * GroupLds<NC, G>::template of<Item>());
 }
 
 template <class Item, int NC, int G>
@@ -624,9 +737,17 @@ int run_persistent_stage_group(const Ctx<NC> &c, const ptflash_problem *p,
 {
     const int block = o->block > 0 ? o->block : tuned_block(NC, Item::kPerMixture);
     if (block % 64 != 0 || block > kBlock) return PTFLASH_EINVAL;
-    const int grid = grid_for((const void *)stage_persistent_group<Item, NC, G>, block, o->grid);
+    const size_t lds = group_lds_bytes<Item, NC, G>(block);
+    int dev = 0, lds_max = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+            hipSuccess)
+        return PTFLASH_EHIP;
+    if (lds > (size_t)lds_max) return PTFLASH_EINVAL;   // a smaller block fits
+    const int grid = grid_for((const void *)stage_persistent_group<Item, NC, G>, block, o->grid,
+                              p->n, G, lds);
     if (grid <= 0) return PTFLASH_EHIP;
-    hipLaunchKernelGGL((stage_persistent_group<Item, NC, G>), dim3(grid), dim3(block), 0, s, c,
+    hipLaunchKernelGGL((stage_persistent_group<Item, NC, G>), dim3(grid), dim3(block), lds, s, c,
                        p->Tc, p->Pc, p->omega, p->kij, c.L.cnt(take_slot));
     return hipGetLastError() == hipSuccess ? PTFLASH_OK : PTFLASH_EHIP;
 }
@@ -661,7 +782,15 @@ int lanes_sp(const ptflash_options *o, bool pm)
     return lanes_ok<NC>(l);
 }
 
-// One trust-region stage (Item1: one mixture per lane; ItemG<G>: groups).
+// The two substitution stages: lanes_ss, else tuned.
+template <int NC>
+int lanes_ss(const ptflash_options *o, bool pm)
+{
+    return lanes_ok<NC>(o->lanes_ss > 0 ? o->lanes_ss : tuned_lanes_ss(NC, pm));
+}
+
+// One stage with a group form (Item1: one mixture per lane; ItemG<G>:
+// groups).
 template <template <int, bool> class Item1, template <int, bool, int> class ItemG, int NC,
           bool PM>
 int run_tr_stage(const Ctx<NC> &c, const ptflash_problem *p, const ptflash_options *o,
@@ -683,8 +812,8 @@ template <int NC, bool PM>
 int launch_persistent(const FlashArgs &a, const ptflash_problem *p, const ptflash_options *o,
                       void *ws, hipStream_t s)
 {
-    const int lsa = lanes_sa<NC>(o, PM), lsp = lanes_sp<NC>(o, PM);
-    if (lsa == 0 || lsp == 0) return PTFLASH_EINVAL;
+    const int lsa = lanes_sa<NC>(o, PM), lsp = lanes_sp<NC>(o, PM), lss = lanes_ss<NC>(o, PM);
+    if (lsa == 0 || lsp == 0 || lss == 0) return PTFLASH_EINVAL;
     Ctx<NC> c;
     char *tail;
     setup_ctx<NC>(c, a, p->n, ws, &tail);
@@ -692,11 +821,11 @@ int launch_persistent(const FlashArgs &a, const ptflash_problem *p, const ptflas
     int rc;
     if ((rc = run_persistent_stage<FeedItem<NC, PM>, NC>(c, p, o, kTake0 + 0, s))) return rc;
     if ((rc = run_persistent_stage<PreSsItem<NC, PM>, NC>(c, p, o, kTake0 + 1, s))) return rc;
-    if ((rc = run_persistent_stage<SaSsItem<NC, PM>, NC>(c, p, o, kTake0 + 2, s))) return rc;
+    if ((rc = run_tr_stage<SaSsItem, SaSsGroup, NC, PM>(c, p, o, lss, kTake0 + 2, s))) return rc;
     if ((rc = run_tr_stage<SaTrItem, SaTrGroup, NC, PM>(c, p, o, lsa, kTake0 + 3, s))) return rc;
     if ((rc = run_persistent_stage<SaFinItem<NC, PM>, NC>(c, p, o, kTake0 + 4, s))) return rc;
     if (a.stability_only) return PTFLASH_OK;
-    if ((rc = run_persistent_stage<SpSsItem<NC, PM>, NC>(c, p, o, kTake0 + 5, s))) return rc;
+    if ((rc = run_tr_stage<SpSsItem, SpSsGroup, NC, PM>(c, p, o, lss, kTake0 + 5, s))) return rc;
     if ((rc = run_tr_stage<SpNtItem, SpNtGroup, NC, PM>(c, p, o, lsp, kTake0 + 6, s))) return rc;
     return PTFLASH_OK;
 }
@@ -749,6 +878,22 @@ int run_plain_stage(const Ctx<NC> &c, const ptflash_problem *p, char *tail, hipS
 }
 
 template <int NC, bool PM>
+int launch_fused(const FlashArgs &a, const ptflash_problem *p, const ptflash_options *o,
+                 void *ws, hipStream_t s)
+{
+    const int block = o->block > 0 ? o->block : 64;
+    if (block % 64 != 0 || block > kBlock) return PTFLASH_EINVAL;
+    Ctx<NC> c;
+    char *tail;
+    setup_ctx<NC>(c, a, p->n, ws, &tail);
+    const int64_t blocks = (p->n + block - 1) / block;
+    if (blocks > 0)
+        hipLaunchKernelGGL((stage_fused<NC, PM>), dim3((unsigned)blocks), dim3(block), 0, s, c,
+                           p->Tc, p->Pc, p->omega, p->kij);
+    return hipGetLastError() == hipSuccess ? PTFLASH_OK : PTFLASH_EHIP;
+}
+
+template <int NC, bool PM>
 int launch_plain(const FlashArgs &a, const ptflash_problem *p, void *ws, hipStream_t s)
 {
     Ctx<NC> c;
@@ -787,11 +932,25 @@ size_t nc_workspace_bytes(int64_t n, int form)
     return workspace_bytes<NC>(n, form);
 }
 
+// Batches up to this many mixture-components (n nc) run the persistent form
+// as one fused launch unless the caller sets its launch shape (grid, block
+// or lanes per mixture): below it the staged form's time is the sum of its
+// stages' slowest items, which the fused form's slowest whole path undercuts
+// (gfx950, measured at nc 3, 8 and 20).
+constexpr int64_t kFusedMaxNNc = 600000;
+
 template <int NC, bool PM>
 int nc_flash_pm(const FlashArgs &a, const ptflash_problem *p, const ptflash_options *o, void *ws,
                 hipStream_t s)
 {
     if (o->form == PTFLASH_FORM_PLAIN) return launch_plain<NC, PM>(a, p, ws, s);
+    if (o->form == PTFLASH_FORM_FUSED) return launch_fused<NC, PM>(a, p, o, ws, s);
+    if (o->grid <= 0 && o->block <= 0 && o->lanes_per_mixture <= 0 && o->lanes_split <= 0 &&
+        o->lanes_ss <= 0 && p->n * NC <= kFusedMaxNNc) {
+        ptflash_options f = *o;
+        f.block = 64;
+        return launch_fused<NC, PM>(a, p, &f, ws, s);
+    }
     return launch_persistent<NC, PM>(a, p, o, ws, s);
 }
 

@@ -405,11 +405,13 @@ static bool options_ok(const ptflash_options *o)
            o->max_tr_split >= 0 && o->max_polish >= 0 && o->dem_every >= 0 &&
            o->tol_sa_ss > 0 && o->tol_sa_tr > 0 && o->tol_split_ss > 0 && o->tol_split_tr > 0 &&
            o->tol_polish > 0 && o->eps_tm >= 0 &&
-           (o->form == PTFLASH_FORM_PERSISTENT || o->form == PTFLASH_FORM_PLAIN) &&
+           (o->form == PTFLASH_FORM_PERSISTENT || o->form == PTFLASH_FORM_PLAIN ||
+            o->form == PTFLASH_FORM_FUSED) &&
            (o->lanes_per_mixture == 0 || o->lanes_per_mixture == 1 ||
             o->lanes_per_mixture == 16 || o->lanes_per_mixture == 32) &&
            (o->lanes_split == 0 || o->lanes_split == 1 || o->lanes_split == 16 ||
-            o->lanes_split == 32);
+            o->lanes_split == 32) &&
+           (o->lanes_ss == 0 || o->lanes_ss == 1 || o->lanes_ss == 16 || o->lanes_ss == 32);
 }
 
 }  // namespace ptf
@@ -440,6 +442,7 @@ void ptflash_default_options(ptflash_options *o)
     o->grid = 0;
     o->lanes_per_mixture = 0;
     o->lanes_split = 0;
+    o->lanes_ss = 0;
 }
 
 int32_t ptflash_max_nc(void) { return kMaxNc; }

@@ -210,6 +210,36 @@ def test_plain_form_bitwise_equal_to_persistent(maker, n):
         assert np.array_equal(a[k], b[k], equal_nan=True), k
 
 
+@pytest.mark.parametrize("maker,n,kw", [
+    (workloads.nc3_workload, 10_000, {}),
+    (workloads.nc8_workload, 20_000, {"keep_factor": True}),
+    (_nc20_shared, 2000, {}),
+    (lambda n: workloads.uniform_workload("fpm", 77, n, 6, 0.5, (200.0, 600.0), (1e5, 2e7),
+                                          per_mixture=True), 5000, {})])
+def test_fused_form_bitwise_equal_to_persistent(maker, n, kw):
+    # the fused form (one lane carries a mixture through every stage, no
+    # lists, no stage barriers) runs the items of the staged forms back to
+    # back: every output equals the persistent form's bit for bit
+    w = maker(n=n)
+    print(f"case fused {w.name} n={n} {kw}", flush=True)
+    a = _run(w, lanes_per_mixture=1, **kw)
+    b = _run(w, form=_capi.FORM_FUSED, **kw)
+    keys = ["label", "beta", "x", "y", "iters", "status", "flops"] + (["factor"] if kw else [])
+    for k in keys:
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+    assert (a["label"] == 1).mean() > 0.05
+    # the stability analysis alone, and a batch of one
+    sa = api.stability(w.z, w.T, w.P, w.Tc, w.Pc, w.omega, w.kij, lanes_per_mixture=1)
+    sb = api.stability(w.z, w.T, w.P, w.Tc, w.Pc, w.omega, w.kij, form=_capi.FORM_FUSED)
+    torch.cuda.synchronize()
+    for k in ("label", "tm", "iters", "status", "flops"):
+        assert torch.equal(getattr(sa, k), getattr(sb, k)), k
+    one = w.subset([n // 2])
+    c = _run(one, form=_capi.FORM_FUSED)
+    for k in ("label", "beta", "x", "y", "iters", "status"):
+        assert np.array_equal(c[k][0], a[k][n // 2], equal_nan=True), k
+
+
 def test_eval_phase_dense_liquid_roots_along_split_paths():
     # Regression: compositions met along the split substitution of dense
     # liquid/vapour pairs (Z close to B), where a Halley iterate landed exactly

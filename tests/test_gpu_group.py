@@ -1,5 +1,6 @@
-"""The trust-region stages with one lane group per mixture (lanes_per_mixture
-16 or 32; lane i holds component i) against the CPU oracle, against the
+"""The stages with one lane group per mixture (the trust-region stages with
+lanes_per_mixture / lanes_split 16 or 32, the substitution stages with
+lanes_ss; lane i holds component i) against the CPU oracle, against the
 one-mixture-per-lane form, and their option checks.
 
 Sizes: 3,000 mixtures per case (many groups per wavefront and a ragged
@@ -26,9 +27,9 @@ def _run(w, **kw):
     return gpu_to_numpy(r)
 
 
-def _check(w, lanes, tag, split=0):
-    print(f"case {tag} nc={w.nc} lanes={lanes}/{split} n={w.n}", flush=True)
-    g = _run(w, lanes_per_mixture=lanes, lanes_split=split)
+def _check(w, lanes, tag, split=0, ss=1, min2=0.08):
+    print(f"case {tag} nc={w.nc} lanes={lanes}/{split}/{ss} n={w.n}", flush=True)
+    g = _run(w, lanes_per_mixture=lanes, lanes_split=split, lanes_ss=ss)
     inv = invariants(w, g)
     print(f"[{tag} invariants] {inv}", flush=True)
     assert inv["mass_balance"] < 1e-13 and inv["sum_x"] < 1e-13 and inv["sum_y"] < 1e-13
@@ -36,10 +37,10 @@ def _check(w, lanes, tag, split=0):
     o = oracle.flash(w, threads=8, want_min_tpd=1)
     rep = compare(g, o, w=w)
     print(f"[{tag}] {rep}", flush=True)
-    assert_parity(rep, o, path_agree=0.97, min_two_phase_frac=0.08)
+    assert_parity(rep, o, path_agree=0.97, min_two_phase_frac=min2)
     # against one mixture per lane: the same decisions; values to rounding
     # wherever both converged
-    one = _run(w, lanes_per_mixture=1)
+    one = _run(w, lanes_per_mixture=1, lanes_ss=1)
     ok = ((g["status"].astype(np.int64) | one["status"].astype(np.int64)) & 0x20) == 0
     assert np.array_equal(g["label"][ok], one["label"][ok])
     two = ok & (g["label"] == 1)
@@ -76,11 +77,25 @@ def test_mixed_stage_widths_parity(nc, sa, sp):
     _check(w, sa, f"mixed nc{nc}", split=sp)
 
 
+@pytest.mark.parametrize("nc,tr,ss", [(12, 1, 16), (16, 16, 16), (20, 1, 32), (20, 32, 32)])
+def test_group_substitution_stages_parity(nc, tr, ss):
+    # the two substitution stages (stability trials, split) with lane groups,
+    # alone or with group trust-region stages; shared and per-mixture sets
+    w = workloads.uniform_workload(f"ss{nc}", 5000 + nc, 3000, nc, 0.5, (200.0, 600.0),
+                                   (1e5, 2e7))
+    # (these seeded sets hold 5-10 % two-phase mixtures: a few hundred
+    # compared splits each)
+    _check(w, tr, f"group substitutions nc{nc}", ss=ss, min2=0.05)
+    w = workloads.uniform_workload(f"sspm{nc}", 6000 + nc, 3000, nc, 0.5, (200.0, 600.0),
+                                   (1e5, 2e7), per_mixture=True)
+    _check(w, tr, f"group substitutions per-mixture nc{nc}", ss=ss, min2=0.05)
+
+
 def test_group_deterministic_across_runs_and_grids():
     w = workloads.uniform_workload("d20", 77, 4000, 20, 0.3, (200.0, 600.0), (1e5, 3e7))
-    a = _run(w, lanes_per_mixture=32)
-    b = _run(w, lanes_per_mixture=32)
-    c = _run(w, lanes_per_mixture=32, grid=7, block=64)
+    a = _run(w, lanes_per_mixture=32, lanes_ss=32)
+    b = _run(w, lanes_per_mixture=32, lanes_ss=32)
+    c = _run(w, lanes_per_mixture=32, lanes_ss=32, grid=7, block=64)
     for k in ("label", "beta", "x", "y", "iters", "status", "flops"):
         assert np.array_equal(a[k], b[k], equal_nan=True), k
         assert np.array_equal(a[k], c[k], equal_nan=True), k
@@ -128,8 +143,13 @@ def test_lanes_option_checked():
         _run(w20, lanes_per_mixture=1, lanes_split=16)   # split group too small
     with pytest.raises(RuntimeError):
         _run(w, lanes_split=32)   # nc = 4
-    assert o.lanes_split == 0
+    with pytest.raises(RuntimeError):
+        _run(w20, lanes_ss=16)    # substitution group too small
+    with pytest.raises(RuntimeError):
+        _run(w20, lanes_ss=8)
+    assert o.lanes_split == 0 and o.lanes_ss == 0
     _run(w20, lanes_per_mixture=32)
     _run(w20, lanes_per_mixture=1)
     _run(w20, lanes_per_mixture=1, lanes_split=32)
+    _run(w20, lanes_ss=32)
     assert L is not None and isinstance(o, C.Structure)
