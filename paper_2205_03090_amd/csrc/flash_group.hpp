@@ -6,10 +6,12 @@
 // Hessian, its Cholesky factor and the composition derivatives of two phases
 // per lane: 3 nc(nc+1)/2 doubles, which at nc = 20 is several KB per lane and
 // spills.  Here lane i of a group holds component i: its composition and
-// gradient entries, row i of the Hessian and row i of the factor.  Both rows
-// live in the group's LDS region, not in registers, and the loops over
-// components run rolled (a few iterations unrolled), so that the registers a
-// lane needs do not grow with nc.  Sums over components are butterfly
+// gradient entries, row i of the Hessian and row i of the factor.  The
+// Hessian row lives in the group's LDS region and the loops over it run
+// rolled (a few iterations unrolled), so that it costs no registers; the
+// factor row is kept both in LDS (the back substitution reads its columns)
+// and in registers, where the factorisation and the forward substitution
+// read it in unrolled loops.  Sums over components are butterfly
 // reductions inside the group (every lane ends with the same bits:
 // floating-point addition is commutative), vectors that every row needs are
 // broadcast through the LDS region, and the back substitution reads the
@@ -213,30 +215,32 @@ __device__ __forceinline__ void phase_derivs_g(double &hdiag, const PhaseG &o,
 // Cholesky factor of H + shift I, H = M + diag(dadd) with M given by the
 // LDS rows (g.hr()) and dadd this lane's diagonal addend: the factor in the
 // group's LDS, row gi by this lane (entries past the diagonal are not
-// meaningful; the diagonal is written by lane j at step j), 1/L_ii of this
-// row in dinv.  Returns whether every pivot was positive (the same in every
-// lane).  As cholesky.
+// meaningful; the diagonal is written by lane j at step j), the same row in
+// lr (registers: the loops over it run unrolled, so that a lane's own
+// factor entries are register reads and each multiply-add reads one LDS
+// value, broadcast), 1/L_ii of this row in dinv.  Returns whether every
+// pivot was positive (the same in every lane).  As cholesky.
 template <int NC, int G>
-__device__ __forceinline__ bool chol_g(double &dinv, double dadd, double shift,
-                                       const Grp<NC, G> &g, uint32_t &fl)
+__device__ __forceinline__ bool chol_g(double (&lr)[NC], double &dinv, double dadd,
+                                       double shift, const Grp<NC, G> &g, uint32_t &fl)
 {
     constexpr int LD = Grp<NC, G>::LD;
     double *Ls = g.lsh();
     double *mine = Ls + g.row * LD;
     const double *hr = g.hr();
     bool ok = true;
-#pragma unroll 1
+#pragma unroll
     for (int j = 0; j < NC; ++j) {
         double s = hr[j];
-        const double *lj = Ls + j * LD;
-#pragma unroll 4
-        for (int k = 0; k < j; ++k) s -= mine[k] * lj[k];
+#pragma unroll
+        for (int k = 0; k < j; ++k) s -= lr[k] * Ls[j * LD + k];
         // lane j's s is the pivot (before its diagonal terms)
         const double piv = gbcast(s + dadd, g.base, j) + shift;
         ok = ok && (piv > 0.0);
         const double d = sqrt(fmax(piv, 1e-300));
         const double dj = 1.0 / d;
-        mine[j] = s * dj;
+        lr[j] = s * dj;
+        mine[j] = lr[j];
         Ls[j * LD + j] = d;
         wave_lds_sync();
     }
@@ -245,18 +249,19 @@ __device__ __forceinline__ bool chol_g(double &dinv, double dadd, double shift,
     return ok;
 }
 
-// y = L^-1 b (forward substitution; this lane's entries of b and y).
+// y = L^-1 b (forward substitution; this lane's entries of b and y, its
+// factor row in lr).
 template <int NC, int G>
-__device__ __forceinline__ double lower_solve_g(double dinv, double b, const Grp<NC, G> &g)
+__device__ __forceinline__ double lower_solve_g(const double (&lr)[NC], double dinv, double b,
+                                                const Grp<NC, G> &g)
 {
-    const double *mine = g.lsh() + g.row * Grp<NC, G>::LD;
     double *yv = g.vec(1);
     double r = b;
-#pragma unroll 2
+#pragma unroll
     for (int j = 0; j < NC; ++j) {
         const double yj = gbcast(r * dinv, g.base, j);
         yv[j] = yj;
-        r -= mine[j] * yj;   // used by the lanes past j only
+        r -= lr[j] * yj;   // used by the lanes past j only
     }
     wave_lds_sync();
     const double y = yv[g.act ? g.gi : 0];
@@ -309,13 +314,14 @@ __device__ __forceinline__ double trust_step_g(double &u, double &radius, bool &
                                                double gv, const Grp<NC, G> &g, uint32_t &fl,
                                                bool newton_only = false)
 {
+    double lr[NC];   // this lane's row of the last factor
     const double mg = -gv;
     eta0 = false;
     bool have = false;
     double eta1 = -1.0;
     u = 0.0;
-    if (chol_g<NC, G>(dinv, dadd, 0.0, g, fl)) {
-        const double y = lower_solve_g<NC, G>(dinv, mg, g);
+    if (chol_g<NC, G>(lr, dinv, dadd, 0.0, g, fl)) {
+        const double y = lower_solve_g<NC, G>(lr, dinv, mg, g);
         u = upper_solve_g<NC, G>(dinv, y, g);
         fl += Cost<NC>::trisolve;
         const double nu = sqrt(gsum<G>(u * u));
@@ -324,7 +330,7 @@ __device__ __forceinline__ double trust_step_g(double &u, double &radius, bool &
             eta0 = true;
             have = true;
         } else {
-            const double q = lower_solve_g<NC, G>(dinv, u, g);
+            const double q = lower_solve_g<NC, G>(lr, dinv, u, g);
             const double nq = sqrt(gsum<G>(q * q));
             eta1 = (nu / nq) * (nu / nq) * (nu - radius) / radius;
             fl += NC * NC + 2 * NC + 6;
@@ -346,12 +352,12 @@ __device__ __forceinline__ double trust_step_g(double &u, double &radius, bool &
         double eta = elo > 0.0 ? elo : 1e-3 * ehi;
         if (eta1 > 0.0 && eta1 < ehi) eta = eta1;
         for (int it = 0; it < 12; ++it) {
-            if (!chol_g<NC, G>(dinv, dadd, eta, g, fl)) {
+            if (!chol_g<NC, G>(lr, dinv, dadd, eta, g, fl)) {
                 elo = eta;
                 eta = fmax(sqrt(elo * ehi), elo + 1e-3 * (ehi - elo));
                 continue;
             }
-            const double y = lower_solve_g<NC, G>(dinv, mg, g);
+            const double y = lower_solve_g<NC, G>(lr, dinv, mg, g);
             const double ut = upper_solve_g<NC, G>(dinv, y, g);
             fl += Cost<NC>::trisolve;
             const double nu = sqrt(gsum<G>(ut * ut));
@@ -359,7 +365,7 @@ __device__ __forceinline__ double trust_step_g(double &u, double &radius, bool &
             have = true;
             if (nu > 0.9 * radius && nu < 1.1 * radius) break;
             if (nu > radius) elo = eta; else ehi = eta;
-            const double q = lower_solve_g<NC, G>(dinv, ut, g);
+            const double q = lower_solve_g<NC, G>(lr, dinv, ut, g);
             const double nq = sqrt(gsum<G>(q * q));
             double en = eta + (nu / nq) * (nu / nq) * (nu - radius) / radius;
             if (!(en > elo && en < ehi)) en = fmax(sqrt(elo * ehi), elo + 1e-3 * (ehi - elo));
