@@ -137,8 +137,9 @@ def bench_ragged(args):
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     t = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev).contiguous()
-    args_t = (t(w.z), t(w.T), t(w.P), w.nc_of, w.off, w.koff, t(w.Tc), t(w.Pc), t(w.omega),
-              t(w.kij))
+    ti = lambda a, dt: torch.as_tensor(a, dtype=dt, device=dev).contiguous()
+    args_t = (t(w.z), t(w.T), t(w.P), ti(w.nc_of, torch.int32), ti(w.off, torch.int64),
+              ti(w.koff, torch.int64), t(w.Tc), t(w.Pc), t(w.omega), t(w.kij))
     out = api.flash_ragged(*args_t)
     torch.cuda.synchronize()
     for _ in range(max(0, args.warmup - 1)):

@@ -263,13 +263,13 @@ def _check_ragged(n, tot, P, nc_of, off, koff, Tc, Pc, omega, kij):
             raise ValueError(f"{name} must be packed like z: shape ({tot},)")
     if n == 0:
         return
-    o = off.cpu()
-    if int(o[0]) != 0 or int(o[-1]) != tot or bool((o[1:] < o[:-1]).any()):
+    # on the arrays' own device, one host read for all of the checks
+    nco = nc_of.to(torch.int64)
+    bad = torch.stack([off[0] != 0, off[-1] != tot, (off[1:] < off[:-1]).any()])
+    if bool(bad.any()):
         raise ValueError("off must start at 0, never decrease and end at len(z)")
-    k = koff.cpu()
-    nco = nc_of.cpu().to(torch.int64)
-    if bool((k < 0).any()) or bool((nco < 0).any()) or \
-            int((k + nco * nco).max()) > kij.shape[0]:
+    bad = torch.stack([(koff < 0).any(), (nco < 0).any(), (koff + nco * nco).max() > kij.shape[0]])
+    if bool(bad.any()):
         raise ValueError("every k block koff[m] + nc_of[m]^2 must lie inside kij")
 
 
