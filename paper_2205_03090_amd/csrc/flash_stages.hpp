@@ -647,7 +647,10 @@ struct SaSsItem {
 // ---------------------------------------------------------------------------
 template <int NC, bool PM>
 struct SaTrItem {
-    static constexpr int WAVES = 1;   // minimum wavefronts per SIMD
+    // two wavefronts per SIMD up to nc = 8: the item holds only ln W across
+    // steps (the EOS constants, the feed reference and the last accepted point
+    // stay in the record)
+    static constexpr int WAVES = (NC <= 8 ? 2 : 1);   // minimum wavefronts per SIMD
     static constexpr bool kPerMixture = PM;   // one component set per mixture
     static constexpr uint32_t OUT = 0u;   // lists the steps append to
     Outbox ob;   // list entries produced by the current step
@@ -656,8 +659,7 @@ struct SaTrItem {
     static constexpr int NP = Tri<NC>::N;
     int64_t m;
     int t;
-    double lw[NC], lacc[NC], d[NC];
-    Eos<NC> e;
+    double lw[NC];   // the current point; the record's lw[t] holds the last accepted one
     double rad, facc, pred, gacc, zw;   // zw: Z of the previous evaluation
     double slen;   // length of the last step taken, in the region's norm
     bool pend;
@@ -670,12 +672,7 @@ struct SaTrItem {
         t = (int)(id & 1u);
         const MixRec<NC> &r = c.rec[m];
 #pragma unroll
-        for (int i = 0; i < NC; ++i) {
-            e.s[i] = r.s[i];
-            e.b[i] = r.b[i];
-            d[i] = r.d[i];
-            lw[i] = r.lw[t][i];
-        }
+        for (int i = 0; i < NC; ++i) lw[i] = r.lw[t][i];
         fl = r.tfl[t];
         st = r.tst[t];
         rad = 0.0;
@@ -701,6 +698,15 @@ struct SaTrItem {
     {
         const Props pp = mix_props<NC, PM>(c.pr, m);
         const FlashArgs &a = c.a;
+        MixRec<NC> &r = c.rec[m];
+        Eos<NC> e;
+        double d[NC];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            e.s[i] = r.s[i];
+            e.b[i] = r.b[i];
+            d[i] = r.d[i];
+        }
         double W[NC];
 #pragma unroll
         for (int i = 0; i < NC; ++i) W[i] = exp(lw[i]);
@@ -735,7 +741,7 @@ struct SaTrItem {
             if (!accept) {
                 rad = 0.5 * fmin(rad, slen);
 #pragma unroll
-                for (int i = 0; i < NC; ++i) lw[i] = lacc[i];
+                for (int i = 0; i < NC; ++i) lw[i] = r.lw[t][i];
                 if (++steps < kStepGuard) return false;   // re-evaluate there
                 st |= kStSaUnconv;
                 done(c, facc);
@@ -782,7 +788,7 @@ struct SaTrItem {
         }
 #pragma unroll
         for (int i = 0; i < NC; ++i) {
-            lacc[i] = lw[i];
+            r.lw[t][i] = lw[i];
             lw[i] = 2.0 * log(sqrt(W[i]) + 0.5 * amax * u[i]);
         }
         fl += 6 * NC;
