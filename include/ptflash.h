@@ -82,12 +82,14 @@ extern "C" {
 
 /* ---- execution forms ---- */
 #define PTFLASH_FORM_PERSISTENT 0 /* one launch per stage; waves refill finished
-                                     lanes.  A batch of n mixtures with
-                                     n * nc <= 600000 and grid, block and the
-                                     lanes options all 0 runs as FUSED     */
+                                     lanes.  With grid, block and the lanes
+                                     options all 0, a batch of n mixtures runs
+                                     as FUSED when n <= 150000 (nc <= 8) or
+                                     n * nc <= 400000 (nc > 8)            */
 #define PTFLASH_FORM_PLAIN 1      /* one launch per stage iteration + compaction */
-#define PTFLASH_FORM_FUSED 2      /* one launch; each lane carries one mixture
-                                     through every stage (small batches) */
+#define PTFLASH_FORM_FUSED 2      /* one launch; a lane pair carries one mixture
+                                     through every stage, its two stability
+                                     trials side by side (small batches)  */
 
 /* Problem description.  Every mixture has the same nc (2 <= nc <= the value
  * of ptflash_max_nc()).  props_per_mixture = 0: Tc, Pc, omega hold nc values

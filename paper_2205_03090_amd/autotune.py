@@ -11,6 +11,15 @@ block, each step keeping the best so far.
 writes DIR/tuned_gfx950.hpp (the table the library compiles in as its
 default, csrc/tuned_gfx950.hpp; component counts outside --nc keep the
 current entries) and DIR/autotune_gfx950.md (the timings).
+
+  python -m paper_2205_03090_amd.autotune --out DIR --crossover
+
+times, for small and medium batches, the persistent form at its tuned
+launch shape against the fused form (64- and 128-thread blocks) and writes
+DIR/fused_crossover_gfx950.md, the measurement behind the batch size up to
+which a persistent call with the launch shape left to the library runs
+fused (fused_max_n in csrc/flash_launch.hpp).  Sample: uniform_workload(seed
+32000 + nc, alpha 0.5, the same T and P ranges).
 The sample for nc is uniform_workload(seed 30000 + nc, alpha 0.5,
 T in [200, 600] K, P in [1e5, 2e7] Pa) with one shared component set, and
 per_mixture_workload_vec(seed 31000 + nc, same distributions) with one set
@@ -120,6 +129,64 @@ constexpr int tuned_block(int nc, bool pm)
 """
 
 
+CROSS_NC = (3, 5, 8, 12, 16, 20)
+CROSS_N = (1_000, 3_000, 10_000, 30_000, 100_000, 300_000)
+
+
+def fused_default(nc: int, n: int) -> bool:
+    """The library's rule (fused_max_n) for a call that leaves the launch
+    shape to it."""
+    return n <= (150_000 if nc <= 8 else 400_000 // nc)
+
+
+def crossover(a):
+    import torch
+    from . import api
+    dev = torch.device("cuda", 0)
+    t = lambda x: torch.as_tensor(x, dtype=torch.float64, device=dev).contiguous()
+    _, _, _, blocks = current_table()
+    lines = ["# Fused against persistent form by batch size (gfx950)", "",
+             f"Command: `python -m paper_2205_03090_amd.autotune --out <dir> --crossover "
+             f"--reps {a.reps}`", "",
+             "Sample per (nc, n): uniform_workload(seed 32000 + nc, alpha 0.5, T in [200, 600] K, "
+             f"P in [1e5, 2e7] Pa, one shared set); median of {a.reps} timed flashes after two "
+             "untimed ones (host clock around each call, launch included). The persistent "
+             "form runs at the tuned launch shape; 'default' is the form a call that leaves "
+             "the launch shape to the library takes.", "",
+             "| nc | n | persistent ms | fused ms (64) | fused ms (128) | default | "
+             "default is the faster |", "|---|---|---|---|---|---|---|"]
+    for nc in CROSS_NC:
+        for n in CROSS_N:
+            if n * nc > 2_000_000:
+                continue
+            w = workloads.uniform_workload(f"cross{nc}", 32_000 + nc, n, nc, 0.5,
+                                           (200.0, 600.0), (1.0e5, 2.0e7))
+            args = [t(v) for v in (w.z, w.T, w.P, w.Tc, w.Pc, w.omega, w.kij)]
+            ms = {}
+            for name, kw in (("pers", dict(block=blocks[0][nc])),
+                             ("f64", dict(form=_capi.FORM_FUSED, block=64)),
+                             ("f128", dict(form=_capi.FORM_FUSED, block=128))):
+                out = api.flash(*args, **kw)
+                api.flash(*args, out=out, **kw)
+                ts = []
+                for _ in range(a.reps):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    api.flash(*args, out=out, **kw)
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t0)
+                ms[name] = 1e3 * float(np.median(ts))
+            fused = fused_default(nc, n)
+            ok = (ms["f64"] <= ms["pers"]) == fused
+            lines.append(f"| {nc} | {n} | {ms['pers']:.3f} | {ms['f64']:.3f} | "
+                         f"{ms['f128']:.3f} | {'fused' if fused else 'persistent'} | "
+                         f"{'yes' if ok else 'no'} |")
+            print(lines[-1], flush=True)
+    os.makedirs(a.out, exist_ok=True)
+    with open(os.path.join(a.out, "fused_crossover_gfx950.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
@@ -127,7 +194,10 @@ def main():
     ap.add_argument("--n-pm", type=int, default=1_000_000)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--nc", type=str, default=f"2-{_build.MAX_NC}")
+    ap.add_argument("--crossover", action="store_true")
     a = ap.parse_args()
+    if a.crossover:
+        return crossover(a)
     import torch
     lo, hi = (int(x) for x in a.nc.split("-"))
     dev = torch.device("cuda", 0)

@@ -341,14 +341,15 @@ stage_persistent_group(Ctx<NC> c, const double *__restrict__ Tc, const double *_
     }
 }
 
-// Fused form (small batches): one lane carries one mixture through every
-// stage in the staged order, with no lists and no barrier between the
+// Fused form (small batches): a pair of lanes carries one mixture through
+// every stage in the staged order, with no lists and no barrier between the
 // stages.  The items are those of the staged forms, run back to back; the
 // list entries an item's last step produces name the item that runs next.
-// Every item reads and writes only its own mixture's record, so the results
-// are those of the staged forms bit for bit; the time is that of the
-// slowest mixture's whole path instead of the sum over stages of each
-// stage's slowest item.
+// The first lane of the pair runs the mixture's items, except that each lane
+// runs one of the two stability trials, at the same time.  Every item reads
+// and writes only its own mixture's record, so the results are those of the
+// staged forms bit for bit; the time is that of the slowest mixture's whole
+// path instead of the sum over stages of each stage's slowest item.
 template <class Item, int NC>
 __device__ __forceinline__ void fused_item(const Ctx<NC> &c, uint32_t id, Outbox &next)
 {
@@ -371,22 +372,29 @@ stage_fused(Ctx<NC> c, const double *__restrict__ Tc, const double *__restrict__
             const double *__restrict__ om, const double *__restrict__ K)
 {
     c.pr = Props{Tc, Pc, om, K};
-    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= c.a.n) return;
+    // the two lanes of a pair are neighbours in one wavefront
+    const int64_t m = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 1;
+    const uint32_t t = threadIdx.x & 1u;
+    if (m >= c.a.n) return;   // both lanes of the pair
     const uint32_t id = (uint32_t)m;
     Outbox o;
-    fused_item<FeedItem<NC, PM>, NC>(c, id, o);
-    if (o.l0 == L_PRE) fused_item<PreSsItem<NC, PM>, NC>(c, id, o);
-    if (o.l0 == L_SA) {
-        // the two stability trials, then the decision (list L_SAFIN)
-        for (uint32_t t = 0; t < 2; ++t) {
-            Outbox q;
-            fused_item<SaSsItem<NC, PM>, NC>(c, 2 * id + t, q);
-            if (q.l0 == L_SATR) fused_item<SaTrItem<NC, PM>, NC>(c, 2 * id + t, q);
-        }
-        fused_item<SaFinItem<NC, PM>, NC>(c, id, o);
+    o.clear();
+    if (t == 0) {
+        fused_item<FeedItem<NC, PM>, NC>(c, id, o);
+        if (o.l0 == L_PRE) fused_item<PreSsItem<NC, PM>, NC>(c, id, o);
     }
-    if (c.a.stability_only) return;
+    // the first lane's routing, and its record writes, to the second lane
+    const int route = __shfl(o.l0, (int)__lane_id() & ~1, 64);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    if (route == L_SA) {
+        // trial t in lane t, then the decision (list L_SAFIN) in the first lane
+        Outbox q;
+        fused_item<SaSsItem<NC, PM>, NC>(c, 2 * id + t, q);
+        if (q.l0 == L_SATR) fused_item<SaTrItem<NC, PM>, NC>(c, 2 * id + t, q);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        if (t == 0) fused_item<SaFinItem<NC, PM>, NC>(c, id, o);
+    }
+    if (t != 0 || c.a.stability_only) return;
     if (o.l0 == L_SPLIT) {
         fused_item<SpSsItem<NC, PM>, NC>(c, id, o);
         if (o.l0 == L_NT || o.l0 == L_NTP) fused_item<SpNtItem<NC, PM>, NC>(c, id, o);
@@ -886,7 +894,7 @@ int launch_fused(const FlashArgs &a, const ptflash_problem *p, const ptflash_opt
     Ctx<NC> c;
     char *tail;
     setup_ctx<NC>(c, a, p->n, ws, &tail);
-    const int64_t blocks = (p->n + block - 1) / block;
+    const int64_t blocks = (2 * p->n + block - 1) / block;   // two lanes per mixture
     if (blocks > 0)
         hipLaunchKernelGGL((stage_fused<NC, PM>), dim3((unsigned)blocks), dim3(block), 0, s, c,
                            p->Tc, p->Pc, p->omega, p->kij);
@@ -932,12 +940,18 @@ size_t nc_workspace_bytes(int64_t n, int form)
     return workspace_bytes<NC>(n, form);
 }
 
-// Batches up to this many mixture-components (n nc) run the persistent form
-// as one fused launch unless the caller sets its launch shape (grid, block
-// or lanes per mixture): below it the staged form's time is the sum of its
-// stages' slowest items, which the fused form's slowest whole path undercuts
-// (gfx950, measured at nc 3, 8 and 20).
-constexpr int64_t kFusedMaxNNc = 600000;
+// Batches up to this many mixtures run the persistent form as one fused
+// launch unless the caller sets its launch shape (grid, block or lanes per
+// mixture): below it the staged form's time is the sum of its stages'
+// slowest items, which the fused form's slowest whole path undercuts.  The
+// fused form keeps a whole mixture on one lane pair, so from nc ~ 12, where
+// the staged form moves the trust-region work onto lane groups, it pays off
+// only for smaller batches (gfx950, measured at nc 3, 5, 8, 12, 16 and 20).
+template <int NC>
+constexpr int64_t fused_max_n()
+{
+    return NC <= 8 ? 150000 : 400000 / NC;
+}
 
 template <int NC, bool PM>
 int nc_flash_pm(const FlashArgs &a, const ptflash_problem *p, const ptflash_options *o, void *ws,
@@ -946,7 +960,7 @@ int nc_flash_pm(const FlashArgs &a, const ptflash_problem *p, const ptflash_opti
     if (o->form == PTFLASH_FORM_PLAIN) return launch_plain<NC, PM>(a, p, ws, s);
     if (o->form == PTFLASH_FORM_FUSED) return launch_fused<NC, PM>(a, p, o, ws, s);
     if (o->grid <= 0 && o->block <= 0 && o->lanes_per_mixture <= 0 && o->lanes_split <= 0 &&
-        o->lanes_ss <= 0 && p->n * NC <= kFusedMaxNNc) {
+        o->lanes_ss <= 0 && p->n <= fused_max_n<NC>()) {
         ptflash_options f = *o;
         f.block = 64;
         return launch_fused<NC, PM>(a, p, &f, ws, s);
