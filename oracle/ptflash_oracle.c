@@ -64,7 +64,10 @@
  *       x = y = z and beta = -1.
  *   R21 a split whose substitution leaves the two-phase region (no
  *       Rachford-Rice root, or theta outside (0,1)), or whose first descent
- *       ends at a degenerate split, restarts once from n^V = beta w, w the
+ *       ends at a degenerate split, at the trivial point x = y or
+ *       unconverged with a phase below 1e-3 of the feed (stalled: kept, and
+ *       the result, flagged unconverged, if the restarted descent ends
+ *       degenerate or trivial), restarts once from n^V = beta w, w the
  *       composition that proved the instability (the stability trial the K
  *       re-estimate uses, or the triage's phase with the smaller tpd), beta
  *       halved from min(1, min z_i/w_i)/2 until G is below the feed's.
@@ -820,6 +823,20 @@ static int orc_is_trivial(int nc, const double *lnW, const double *z)
     return m < 1e-4;
 }
 
+/* A split n^V of the feed z whose phases coincide: max_i |ln(y_i/x_i)| below
+ * 1e-6 (the test the result uses to report a trivial split). */
+static int orc_split_is_trivial(int nc, const double *z, const double *nV, double bv)
+{
+    if (!(bv > 1e-10 && bv < 1.0 - 1e-10)) return 0;
+    double bl = 0.0, lkmax = 0.0;
+    for (int i = 0; i < nc; ++i) bl += z[i] - nV[i];
+    for (int i = 0; i < nc; ++i) {
+        double q = fabs(log((nV[i] / bv) / ((z[i] - nV[i]) / bl)));
+        if (q > lkmax) lkmax = q;
+    }
+    return lkmax < 1e-6;
+}
+
 static void orc_single_phase(int nc, const double *z, orc_result *res)
 {
     res->label = 0;
@@ -1027,16 +1044,38 @@ int orc_flash_one(int nc, const double *z_in, double T, double P,
     if (orc_split_newton(&e, z, nV, o, &nnt) != 0) flags |= ORC_SPLIT_UNCONV;
     double bv = 0.0;
     for (int i = 0; i < nc; ++i) bv += nV[i];
-    if (!(bv > 1e-10 && bv < 1.0 - 1e-10) && !(flags & ORC_SPLIT_RESTART) && have_w &&
-        orc_split_restart(&e, z, d, wst, nV) == 0) {
-        /* R21: the descent ended at a degenerate split; restart once from
-         * the composition that proved the instability */
+    const int degen1 = !(bv > 1e-10 && bv < 1.0 - 1e-10);
+    const int triv1 = orc_split_is_trivial(nc, z, nV, bv);
+    const int stalled = (flags & ORC_SPLIT_UNCONV) && fmin(bv, 1.0 - bv) < 1e-3;
+    double nb[ORC_NCMAX];
+    memcpy(nb, nV, sizeof(double) * nc);
+    int restarted = 0;
+    if ((degen1 || triv1 || stalled) && !(flags & ORC_SPLIT_RESTART) && have_w) {
+        restarted = orc_split_restart(&e, z, d, wst, nV) == 0;
+        /* no start below the feed's G: the first descent's point stands */
+        if (!restarted) memcpy(nV, nb, sizeof(double) * nc);
+    }
+    if (restarted) {
+        /* R21: the descent ended at a degenerate split, at the trivial point
+         * (which an unstable feed's split cannot be: the composition w gives
+         * a lower G) or stalled against the boundary (unconverged, a phase
+         * below 1e-3 of the feed); restart once from the composition that
+         * proved the instability */
         flags = (flags & ~ORC_SPLIT_UNCONV) | ORC_SPLIT_RESTART;
         int n2 = 0;
         if (orc_split_newton(&e, z, nV, o, &n2) != 0) flags |= ORC_SPLIT_UNCONV;
         nnt += n2;
         bv = 0.0;
         for (int i = 0; i < nc; ++i) bv += nV[i];
+        if (stalled && !degen1 && !triv1 &&
+            (!(bv > 1e-10 && bv < 1.0 - 1e-10) || orc_split_is_trivial(nc, z, nV, bv))) {
+            /* the restarted descent failed: the stalled split is the result,
+             * flagged unconverged */
+            memcpy(nV, nb, sizeof(double) * nc);
+            flags |= ORC_SPLIT_UNCONV;
+            bv = 0.0;
+            for (int i = 0; i < nc; ++i) bv += nV[i];
+        }
     }
     res->info[ORC_I_NT_SPLIT] = nnt;
     /* a phase holding less than 1e-10 of the feed: degenerate split */

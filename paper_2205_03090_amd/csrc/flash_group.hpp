@@ -882,6 +882,7 @@ struct SpNtGroup {
     bool spend, spol;
     bool start;    // restart: searching the start point (v1 holds the composition)
     bool restarted;
+    bool back;     // the record holds a stalled first descent's n^V (r.lk)
     int tr, pol, steps, nhalf, rstk;
     int tr0;       // trust-region steps before a restart (each descent has the cap)
     uint32_t fl, status;
@@ -926,7 +927,7 @@ struct SpNtGroup {
         status = r.status;
         srad = 0.0;
         spend = spol = tronly = false;
-        start = restarted = false;
+        start = restarted = back = false;
         tr = pol = steps = tr0 = 0;
         zx = zy = -1.0;
         if (r.rst != 0) set_start(r, r.rst, g);
@@ -964,13 +965,25 @@ struct SpNtGroup {
         }
     }
 
+    // Returns to the stalled split kept in the record (each lane its own
+    // component): the next step evaluates it and, its trust-region budget
+    // spent, reports it unconverged.
+    __device__ __forceinline__ void back_to_stalled(const Ctx<NC> &c, const Grp<NC, G> &g)
+    {
+        v0 = g.act ? c.rec[m].lk[g.gi] : 0.0;
+        back = false;
+        start = spend = spol = tronly = false;
+        tr0 = tr - c.a.max_tr_split;
+    }
+
     // savef: the group's LDS holds the factor of H' at the solution.  As
     // SpNtItem::finish: false when the split restarts instead.
+
     __device__ __forceinline__ bool finish(const Ctx<NC> &c, const Grp<NC, G> &g, double zx_,
                                            double zy_, bool savef, double vs)
     {
         const FlashArgs &a = c.a;
-        const MixRec<NC> &r = c.rec[m];
+        MixRec<NC> &r = c.rec[m];
         int16_t it[8];
         load_it<NC>(it, r);
         it[6] = (int16_t)tr;
@@ -978,12 +991,23 @@ struct SpNtGroup {
         double x, y, bv;
         xy_from_nv(x, y, bv);
         const double lk = gmax<G>(g.act ? fabs(log(y / x)) : 0.0);
-        if (!(bv > kMinPhase && bv < 1.0 - kMinPhase)) {
-            if (!restarted && r.wsel >= 0) {
-                set_start(r, 1, g);
-                status = (status & ~(kStSplitUnconv | kStStepCap)) | kStSplitTr | kStSplitRestart;
-                return false;
+        const bool degenerate = !(bv > kMinPhase && bv < 1.0 - kMinPhase);
+        const bool stalled = (status & kStSplitUnconv) && fmin(bv, 1.0 - bv) < kStalledPhase;
+        if ((degenerate || lk < 1e-6 || stalled) && !restarted && r.wsel >= 0) {
+            if (stalled && !degenerate && !(lk < 1e-6)) {
+                if (g.act) r.lk[g.gi] = v0;
+                back = true;
             }
+            set_start(r, 1, g);
+            status = (status & ~(kStSplitUnconv | kStStepCap)) | kStSplitTr | kStSplitRestart;
+            return false;
+        }
+        if ((degenerate || lk < 1e-6) && back) {
+            // the restarted descent failed: the stalled split is the result
+            back_to_stalled(c, g);
+            return false;
+        }
+        if (degenerate) {
             write_single(c, g, status | kStSplitFailed, it);
             return true;
         }
@@ -1055,6 +1079,12 @@ struct SpNtGroup {
                 start = false;
             } else {
                 if (++nhalf > 30 || ++steps >= kStepGuard) {
+                    if (back) {
+                        // no start below the feed's G: the stalled split stands
+                        back_to_stalled(c, g);
+                        status &= ~kStSplitRestart;
+                        return false;
+                    }
                     int16_t it[8];
                     load_it<NC>(it, c.rec[m]);
                     it[6] = (int16_t)tr;

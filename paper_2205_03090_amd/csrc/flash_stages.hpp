@@ -64,6 +64,10 @@ constexpr uint32_t kStInvalid = 0x0001u, kStShortcut = 0x0002u, kStSaRan = 0x000
 // reported as failed (single phase).
 constexpr double kMinPhase = 1e-10;
 
+// An unconverged split whose smaller phase holds less than this fraction of
+// the feed stalled against the boundary on its way to a degenerate split.
+constexpr double kStalledPhase = 1e-3;
+
 // Per-stage guard on the number of steps of one item (every stage is bounded
 // by its iteration caps; this only guarantees termination).
 constexpr int kStepGuard = 96;
@@ -1039,6 +1043,7 @@ struct SpNtItem {
     bool tronly;   // refinement found H indefinite: take a trust-region step first
     bool start;    // restart: searching the start point (v1 holds the composition)
     bool restarted;
+    bool back;     // the record holds a stalled first descent's point (r.lk)
     int tr, pol, steps, nhalf, rstk;
     int tr0;       // trust-region steps before a restart (each descent has the cap)
     uint32_t fl, status;
@@ -1092,11 +1097,24 @@ struct SpNtItem {
         status = r.status;
         srad = 0.0;
         spend = spol = tronly = false;
-        start = restarted = false;
+        start = restarted = back = false;
         tr = pol = steps = tr0 = 0;
         zx = zy = -1.0;
         if (r.rst != 0) set_start(r, r.rst);
         return true;
+    }
+
+    // Returns to the stalled split kept in the record: the next step
+    // evaluates it and, its trust-region budget spent, reports it
+    // unconverged.
+    __device__ __forceinline__ void back_to_stalled(const Ctx<NC> &c)
+    {
+        const MixRec<NC> &r = c.rec[m];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) v0[i] = r.lk[i];
+        back = false;
+        start = spend = spol = tronly = false;
+        tr0 = tr - c.a.max_tr_split;
     }
 
     // x, y from v0 = n^V: y = n^V/sum n^V, x = (z - n^V)/sum(z - n^V)
@@ -1118,9 +1136,13 @@ struct SpNtItem {
     }
 
     // Writes the outputs and returns true, or, when the split ended
-    // degenerate (a phase below kMinPhase of the feed) and has not been
-    // restarted yet, restarts it from the composition that proved the
-    // instability and returns false.
+    // degenerate (a phase below kMinPhase of the feed), at the trivial point
+    // (no unstable feed's split: the composition that proved the instability
+    // gives a lower G) or unconverged with a phase below kStalledPhase, and
+    // has not been restarted yet, restarts it from that composition and
+    // returns false.  A stalled split is kept in the record (n^V in lk,
+    // unused from here on) and is the result, flagged unconverged, when the
+    // restarted descent ends degenerate or trivial.
     __device__ __forceinline__ bool finish(const Ctx<NC> &c, double zx, double zy,
                                            const double (&Lf)[NP], bool savef,
                                            const double (&vs)[NC])
@@ -1136,12 +1158,24 @@ struct SpNtItem {
         double lk = 0.0;
 #pragma unroll
         for (int i = 0; i < NC; ++i) lk = fmax(lk, fabs(log(y[i] / x[i])));
-        if (!(bv > kMinPhase && bv < 1.0 - kMinPhase)) {
-            if (!restarted && r.wsel >= 0) {
-                set_start(r, 1);
-                status = (status & ~(kStSplitUnconv | kStStepCap)) | kStSplitTr | kStSplitRestart;
-                return false;
+        const bool degenerate = !(bv > kMinPhase && bv < 1.0 - kMinPhase);
+        const bool stalled = (status & kStSplitUnconv) && fmin(bv, 1.0 - bv) < kStalledPhase;
+        if ((degenerate || lk < 1e-6 || stalled) && !restarted && r.wsel >= 0) {
+            if (stalled && !degenerate && !(lk < 1e-6)) {
+#pragma unroll
+                for (int i = 0; i < NC; ++i) r.lk[i] = v0[i];
+                back = true;
             }
+            set_start(r, 1);
+            status = (status & ~(kStSplitUnconv | kStStepCap)) | kStSplitTr | kStSplitRestart;
+            return false;
+        }
+        if ((degenerate || lk < 1e-6) && back) {
+            // the restarted descent failed: the stalled split is the result
+            back_to_stalled(c);
+            return false;
+        }
+        if (degenerate) {
             write_outputs_single<NC>(c, m, z, status | kStSplitFailed, fl, it);
             return true;
         }
@@ -1224,6 +1258,12 @@ struct SpNtItem {
                 start = false;
             } else {
                 if (++nhalf > 30 || ++steps >= kStepGuard) {
+                    if (back) {
+                        // no start below the feed's G: the stalled split stands
+                        back_to_stalled(c);
+                        status &= ~kStSplitRestart;
+                        return false;
+                    }
                     int16_t it[8];
                     load_it<NC>(it, c.rec[m]);
                     it[6] = (int16_t)tr;

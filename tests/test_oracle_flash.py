@@ -286,6 +286,13 @@ def test_every_proven_instability_ends_in_a_valid_split(orc):
     flags = info[:, f["flags"]]
     assert not np.any(unstable & ((flags & orc.FLAG_SPLIT_FAILED) != 0))
     rst = np.where(flags & orc.FLAG_SPLIT_RESTART)[0]
+    # a first descent that ends unconverged restarts too; where the second
+    # descent does not converge either, the split stays flagged unconverged
+    # (the parity tests treat such rows as having no reference); the rest
+    # must be valid splits
+    unc = (flags[rst] & orc.FLAG_SPLIT_UNCONV) != 0
+    assert unc.sum() <= 5, rst[unc]
+    rst = rst[~unc]
     assert len(rst) >= 3, len(rst)   # the restart is exercised
     for m in rst:
         x, y, b = r["x"][m], r["y"][m], r["beta"][m]
