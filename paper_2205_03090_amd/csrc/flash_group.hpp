@@ -1113,98 +1113,106 @@ struct SpNtGroup {
         hdiag = g.act ? (hdiag - vs * vs) * sc : 0.0;
         const double dadd = sc;
         fl += 8 * NP;
-        if (spend) {
-            spend = false;
-            bool accept;
-            double ratio = 1.0;
-            if (fabs(spred) < 1e-13) {
-                accept = gmx < sgacc;
-            } else {
-                ratio = (G_ - sfacc) / spred;
-                accept = (G_ < sfacc) && ratio > 0.0;
+        int fin = 0;   // the split ends here: 1 without the factor, 2 with it
+        do {
+            if (spend) {
+                spend = false;
+                bool accept;
+                double ratio = 1.0;
+                if (fabs(spred) < 1e-13) {
+                    accept = gmx < sgacc;
+                } else {
+                    ratio = (G_ - sfacc) / spred;
+                    accept = (G_ < sfacc) && ratio > 0.0;
+                }
+                // a rejected or poor step halves the radius, from the length of
+                // the step taken when the boundary cut made it shorter
+                if (!accept) {
+                    srad = 0.5 * fmin(srad, slen);
+                    v0 = v1;
+                    if (++steps < kStepGuard) return false;   // re-evaluate there
+                    status |= kStSplitUnconv | kStStepCap;
+                    fin = 1;
+                    break;
+                }
+                if (ratio <= 0.25) srad = 0.5 * fmin(srad, slen);
+                else if (ratio >= 0.75) srad *= 2.0;
             }
-            // a rejected or poor step halves the radius, from the length of
-            // the step taken when the boundary cut made it shorter
-            if (!accept) {
-                srad = 0.5 * fmin(srad, slen);
-                v0 = v1;
-                if (++steps < kStepGuard) return false;   // re-evaluate there
-                status |= kStSplitUnconv | kStStepCap;
-                return finish(c, g, Z0, o.Z, false, vs);
+            if (!spol && !tronly && gmx < a.tol_split_tr) {
+                spol = true;   // the paper's criterion holds: refine
+                sdprev = 1e300;
             }
-            if (ratio <= 0.25) srad = 0.5 * fmin(srad, slen);
-            else if (ratio >= 0.75) srad *= 2.0;
-        }
-        if (!spol && !tronly && gmx < a.tol_split_tr) {
-            spol = true;   // the paper's criterion holds: refine
-            sdprev = 1e300;
-        }
-        // One call site for both the refinement's Newton step and the
-        // trust-region step (as SpNtItem).  Newton refinement runs while H is
-        // positive definite; an indefinite H sends the split back to the
-        // trust region, which starts from the same point at the next step.
-        const bool newton = spol;
-        if (!newton) {
-            if (tr - tr0 >= a.max_tr_split || ++steps >= kStepGuard) {
+            // One call site for both the refinement's Newton step and the
+            // trust-region step (as SpNtItem).  Newton refinement runs while H is
+            // positive definite; an indefinite H sends the split back to the
+            // trust region, which starts from the same point at the next step.
+            const bool newton = spol;
+            if (!newton) {
+                if (tr - tr0 >= a.max_tr_split || ++steps >= kStepGuard) {
+                    status |= kStSplitUnconv;
+                    fin = 1;
+                    break;
+                }
+                status |= kStSplitTr;
+            }
+            double u;
+            bool eta0;
+            double rad = newton ? 1e300 : srad;
+            double pr = trust_step_g<NC, G>(u, rad, eta0, dinv, hdiag, dadd, gs, g, fl, newton);
+            if (newton && !eta0) {
+                spol = false;
+                tronly = true;
+                if (++steps < kStepGuard) return false;
                 status |= kStSplitUnconv;
-                return finish(c, g, Z0, o.Z, false, vs);
+                fin = 1;
+                break;
             }
-            status |= kStSplitTr;
-        }
-        double u;
-        bool eta0;
-        double rad = newton ? 1e300 : srad;
-        double pr = trust_step_g<NC, G>(u, rad, eta0, dinv, hdiag, dadd, gs, g, fl, newton);
-        if (newton && !eta0) {
-            spol = false;
-            tronly = true;
-            if (++steps < kStepGuard) return false;
-            status |= kStSplitUnconv;
-            return finish(c, g, Z0, o.Z, false, vs);
-        }
-        if (!newton) {
-            srad = rad;
-            tronly = false;
-        }
-        if (spol) {
+            if (!newton) {
+                srad = rad;
+                tronly = false;
+            }
+            if (spol) {
+                u *= vs;
+                double lim = 1.0;
+                if (g.act && u < 0.0) lim = fmin(lim, 0.99 * v0 / -u);
+                if (g.act && u > 0.0) lim = fmin(lim, 0.99 * (z - v0) / u);
+                const double dmax = gmax<G>(fabs(u));
+                const double amax = gmin<G>(lim);
+                v0 += amax * u;
+                fl += 6 * NC;
+                const bool conv = dmax < a.tol_polish || (dmax < 1e-10 && dmax >= 0.5 * sdprev);
+                if (conv || pol >= a.max_polish || ++steps >= kStepGuard) {
+                    if (!conv && !(dmax < 1e-10)) status |= kStSplitUnconv;
+                    fin = 2;
+                    break;
+                }
+                sdprev = dmax;
+                ++pol;
+                return false;
+            }
+            // dn = v o u, kept inside 0 < n^V < z
+            const double nu = sqrt(gsum<G>(g.act ? u * u : 0.0));
             u *= vs;
             double lim = 1.0;
             if (g.act && u < 0.0) lim = fmin(lim, 0.99 * v0 / -u);
             if (g.act && u > 0.0) lim = fmin(lim, 0.99 * (z - v0) / u);
-            const double dmax = gmax<G>(fabs(u));
             const double amax = gmin<G>(lim);
+            if (amax < 1.0) {
+                const double gu = gsum<G>(gt * u);
+                pr = amax * gu + amax * amax * (pr - gu);
+            }
+            slen = amax * nu;
+            v1 = v0;
             v0 += amax * u;
             fl += 6 * NC;
-            const bool conv = dmax < a.tol_polish || (dmax < 1e-10 && dmax >= 0.5 * sdprev);
-            if (conv || pol >= a.max_polish || ++steps >= kStepGuard) {
-                if (!conv && !(dmax < 1e-10)) status |= kStSplitUnconv;
-                return finish(c, g, Z0, o.Z, true, vs);
-            }
-            sdprev = dmax;
-            ++pol;
+            sfacc = G_;
+            sgacc = gmx;
+            spred = pr;
+            spend = true;
+            ++tr;
             return false;
-        }
-        // dn = v o u, kept inside 0 < n^V < z
-        const double nu = sqrt(gsum<G>(g.act ? u * u : 0.0));
-        u *= vs;
-        double lim = 1.0;
-        if (g.act && u < 0.0) lim = fmin(lim, 0.99 * v0 / -u);
-        if (g.act && u > 0.0) lim = fmin(lim, 0.99 * (z - v0) / u);
-        const double amax = gmin<G>(lim);
-        if (amax < 1.0) {
-            const double gu = gsum<G>(gt * u);
-            pr = amax * gu + amax * amax * (pr - gu);
-        }
-        slen = amax * nu;
-        v1 = v0;
-        v0 += amax * u;
-        fl += 6 * NC;
-        sfacc = G_;
-        sgacc = gmx;
-        spred = pr;
-        spend = true;
-        ++tr;
-        return false;
+        } while (false);
+        return finish(c, g, Z0, o.Z, fin == 2, vs);
     }
 };
 

@@ -1290,112 +1290,120 @@ struct SpNtItem {
                 Hs[tri(i, j)] = h * sc;
             }
         fl += 8 * NP;
-        if (spend) {
-            spend = false;
-            bool accept;
-            double ratio = 1.0;
-            if (fabs(spred) < 1e-13) {
-                accept = gmax < sgacc;
-            } else {
-                ratio = (G - sfacc) / spred;
-                accept = (G < sfacc) && ratio > 0.0;
+        int fin = 0;   // the split ends here: 1 without the factor, 2 with it
+        do {
+            if (spend) {
+                spend = false;
+                bool accept;
+                double ratio = 1.0;
+                if (fabs(spred) < 1e-13) {
+                    accept = gmax < sgacc;
+                } else {
+                    ratio = (G - sfacc) / spred;
+                    accept = (G < sfacc) && ratio > 0.0;
+                }
+                // a rejected or poor step halves the radius, from the length of
+                // the step taken when the boundary cut made it shorter
+                if (!accept) {
+                    srad = 0.5 * fmin(srad, slen);
+    #pragma unroll
+                    for (int i = 0; i < NC; ++i) v0[i] = v1[i];
+                    if (++steps < kStepGuard) return false;   // re-evaluate there
+                    status |= kStSplitUnconv | kStStepCap;
+                    fin = 1;
+                    break;
+                }
+                if (ratio <= 0.25) srad = 0.5 * fmin(srad, slen);
+                else if (ratio >= 0.75) srad *= 2.0;
             }
-            // a rejected or poor step halves the radius, from the length of
-            // the step taken when the boundary cut made it shorter
-            if (!accept) {
-                srad = 0.5 * fmin(srad, slen);
-#pragma unroll
-                for (int i = 0; i < NC; ++i) v0[i] = v1[i];
-                if (++steps < kStepGuard) return false;   // re-evaluate there
-                status |= kStSplitUnconv | kStStepCap;
-                return finish(c, Z0, o.Z, F, false, vs);
+            if (!spol && !tronly && gmax < a.tol_split_tr) {
+                spol = true;   // the paper's criterion holds: refine
+                sdprev = 1e300;
             }
-            if (ratio <= 0.25) srad = 0.5 * fmin(srad, slen);
-            else if (ratio >= 0.75) srad *= 2.0;
-        }
-        if (!spol && !tronly && gmax < a.tol_split_tr) {
-            spol = true;   // the paper's criterion holds: refine
-            sdprev = 1e300;
-        }
-        // One call site for both the refinement's Newton step and the
-        // trust-region step, so that lanes in either mode factor together.
-        // Newton refinement runs while H is positive definite; an indefinite
-        // H sends the split back to the trust region, which starts from the
-        // same point at the next step.
-        const bool newton = spol;
-        if (!newton) {
-            if (tr - tr0 >= a.max_tr_split || ++steps >= kStepGuard) {
+            // One call site for both the refinement's Newton step and the
+            // trust-region step, so that lanes in either mode factor together.
+            // Newton refinement runs while H is positive definite; an indefinite
+            // H sends the split back to the trust region, which starts from the
+            // same point at the next step.
+            const bool newton = spol;
+            if (!newton) {
+                if (tr - tr0 >= a.max_tr_split || ++steps >= kStepGuard) {
+                    status |= kStSplitUnconv;
+                    fin = 1;
+                    break;
+                }
+                status |= kStSplitTr;
+            }
+            double u[NC];
+            bool eta0;
+            double rad = newton ? 1e300 : srad;
+            double pr = trust_step<NC>(u, rad, eta0, F, dinv, Hs, gs, fl, newton);
+            if (newton && !eta0) {
+                spol = false;
+                tronly = true;
+                if (++steps < kStepGuard) return false;
                 status |= kStSplitUnconv;
-                return finish(c, Z0, o.Z, F, false, vs);
+                fin = 1;
+                break;
             }
-            status |= kStSplitTr;
-        }
-        double u[NC];
-        bool eta0;
-        double rad = newton ? 1e300 : srad;
-        double pr = trust_step<NC>(u, rad, eta0, F, dinv, Hs, gs, fl, newton);
-        if (newton && !eta0) {
-            spol = false;
-            tronly = true;
-            if (++steps < kStepGuard) return false;
-            status |= kStSplitUnconv;
-            return finish(c, Z0, o.Z, F, false, vs);
-        }
-        if (!newton) {
-            srad = rad;
-            tronly = false;
-        }
-        if (spol) {
-            double dmax = 0.0, amax = 1.0;
-#pragma unroll
+            if (!newton) {
+                srad = rad;
+                tronly = false;
+            }
+            if (spol) {
+                double dmax = 0.0, amax = 1.0;
+    #pragma unroll
+                for (int i = 0; i < NC; ++i) {
+                    u[i] *= vs[i];
+                    dmax = fmax(dmax, fabs(u[i]));
+                    if (u[i] < 0.0) amax = fmin(amax, 0.99 * v0[i] / -u[i]);
+                    if (u[i] > 0.0) amax = fmin(amax, 0.99 * (z[i] - v0[i]) / u[i]);
+                }
+    #pragma unroll
+                for (int i = 0; i < NC; ++i) v0[i] += amax * u[i];
+                fl += 6 * NC;
+                // converged: step below tol_polish, or rounding-size steps that no
+                // longer shrink
+                const bool conv = dmax < a.tol_polish || (dmax < 1e-10 && dmax >= 0.5 * sdprev);
+                if (conv || pol >= a.max_polish || ++steps >= kStepGuard) {
+                    if (!conv && !(dmax < 1e-10)) status |= kStSplitUnconv;
+                    fin = 2;
+                    break;
+                }
+                sdprev = dmax;
+                ++pol;
+                return false;
+            }
+            // dn = v o u, kept inside 0 < n^V < z
+            const double nu = norm2<NC>(u);
+            double amax = 1.0;
+    #pragma unroll
             for (int i = 0; i < NC; ++i) {
                 u[i] *= vs[i];
-                dmax = fmax(dmax, fabs(u[i]));
                 if (u[i] < 0.0) amax = fmin(amax, 0.99 * v0[i] / -u[i]);
                 if (u[i] > 0.0) amax = fmin(amax, 0.99 * (z[i] - v0[i]) / u[i]);
             }
-#pragma unroll
-            for (int i = 0; i < NC; ++i) v0[i] += amax * u[i];
-            fl += 6 * NC;
-            // converged: step below tol_polish, or rounding-size steps that no
-            // longer shrink
-            const bool conv = dmax < a.tol_polish || (dmax < 1e-10 && dmax >= 0.5 * sdprev);
-            if (conv || pol >= a.max_polish || ++steps >= kStepGuard) {
-                if (!conv && !(dmax < 1e-10)) status |= kStSplitUnconv;
-                return finish(c, Z0, o.Z, F, true, vs);
+            if (amax < 1.0) {
+                double gu = 0.0;
+    #pragma unroll
+                for (int i = 0; i < NC; ++i) gu += gt[i] * u[i];
+                pr = amax * gu + amax * amax * (pr - gu);
             }
-            sdprev = dmax;
-            ++pol;
+            slen = amax * nu;
+    #pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                v1[i] = v0[i];
+                v0[i] += amax * u[i];
+            }
+            fl += 6 * NC;
+            sfacc = G;
+            sgacc = gmax;
+            spred = pr;
+            spend = true;
+            ++tr;
             return false;
-        }
-        // dn = v o u, kept inside 0 < n^V < z
-        const double nu = norm2<NC>(u);
-        double amax = 1.0;
-#pragma unroll
-        for (int i = 0; i < NC; ++i) {
-            u[i] *= vs[i];
-            if (u[i] < 0.0) amax = fmin(amax, 0.99 * v0[i] / -u[i]);
-            if (u[i] > 0.0) amax = fmin(amax, 0.99 * (z[i] - v0[i]) / u[i]);
-        }
-        if (amax < 1.0) {
-            double gu = 0.0;
-#pragma unroll
-            for (int i = 0; i < NC; ++i) gu += gt[i] * u[i];
-            pr = amax * gu + amax * amax * (pr - gu);
-        }
-        slen = amax * nu;
-#pragma unroll
-        for (int i = 0; i < NC; ++i) {
-            v1[i] = v0[i];
-            v0[i] += amax * u[i];
-        }
-        fl += 6 * NC;
-        sfacc = G;
-        sgacc = gmax;
-        spred = pr;
-        spend = true;
-        ++tr;
-        return false;
+        } while (false);
+        return finish(c, Z0, o.Z, F, fin == 2, vs);
     }
 };
 
